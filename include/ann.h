@@ -1,0 +1,256 @@
+/*
+ * ann.h - C ABI of the MI355X (gfx950) library for search over an augmented
+ * neighborhood graph: an exact kNN graph over the reference vectors plus a
+ * bridge graph from Cartesian-concatenated codebook vectors
+ * (Wang et al., "Fast Neighborhood Graph Search using Cartesian
+ * Concatenation", arXiv:1312.3062).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Every call returns ann_status: ANN_OK (0) or a negative error code.  No
+ *    exception crosses the ABI.  ann_last_error() returns a thread-local
+ *    message describing the last failure of the calling thread.
+ *  - On error the index passed in is unchanged and output buffers hold
+ *    undefined contents.
+ *  - "host" pointers point to CPU memory, "device" pointers (d_ prefix) to
+ *    memory on the GPU that holds the index.  All pointers are borrowed for
+ *    the duration of the call only.
+ *  - Distances are SQUARED Euclidean distances (the paper stores the square
+ *    of the distance, Sec. 3.2 and Sec. 4.2).  For ANN_U8 data they are
+ *    exact int32 values; for ANN_F32 data they are float.
+ *  - Result rows hold `k` entries ascending by (distance, id).  When fewer
+ *    than k vectors were evaluated the row is padded with id -1 and
+ *    distance INT32_MAX (u8) or +infinity (f32).
+ *  - Every order and every tie is resolved by the total order on
+ *    (distance, node id).  A bridge vector with linear id lid has node id
+ *    n + lid, so at equal distance a reference vector comes first.
+ *  - The index is read-only after it is built; searches on different
+ *    streams may run concurrently on one index.
+ *  - Results depend only on (index, query, k, budget, queue_len,
+ *    precision): never on batch composition, launch shape or tuning.
+ */
+#ifndef ANN_H
+#define ANN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ann_index ann_index; /* opaque; owned by the library */
+
+typedef enum { ANN_U8 = 0, ANN_F32 = 1 } ann_dtype;
+
+typedef enum {
+    ANN_OK = 0,
+    ANN_EINVAL = -1,       /* invalid argument (null pointer, bad size, dtype mismatch) */
+    ANN_ENOMEM = -2,       /* device or host allocation failed */
+    ANN_EDEVICE = -3,      /* a HIP call failed */
+    ANN_ESTATE = -4,       /* object in the wrong state */
+    ANN_EUNSUPPORTED = -5, /* valid request outside what this build implements */
+    ANN_EIO = -6,          /* file could not be read or written */
+    ANN_ERESOURCE = -7     /* a per-query structure outgrew its capacity */
+} ann_status;
+
+/* Search precision for ANN_F32 indexes.  u8 indexes are always exact. */
+typedef enum {
+    ANN_PRECISION_EXACT = 0,      /* fp32 distances from the fp32 rows */
+    ANN_PRECISION_BF16_RERANK = 1 /* bf16 copies drive the search; final top
+                                     rerank_k re-ranked from the fp32 rows */
+} ann_precision;
+
+/*
+ * Index build parameters (Sec. 4.1 "Data structure").
+ *  graph_k      R, out-degree of the exact kNN graph (row i = the R nearest
+ *               j != i, ascending by (distance, j)).  0 builds no graph.
+ *  P, K         P subspaces of d/P contiguous dims (P divides d); K codewords
+ *               per subspace; K^P bridge vectors.  1 <= P <= 4, 1 <= K <= 256,
+ *               n + K^P < 2^32.
+ *  kmeans_iters Lloyd iterations per subspace (assign, then update).  The K
+ *               initial rows are the first K entries of a Fisher-Yates
+ *               shuffle of [0, n) driven by SplitMix64(seed); ties in
+ *               assignment go to the smaller codeword; u8 centroids are the
+ *               member mean rounded half up; empty clusters keep their
+ *               centroid.
+ *  bridge_t     each reference vector is linked from its bridge_t nearest
+ *               bridge vectors (by (distance, lid)).
+ *  bridge_b     each bridge vector keeps its bridge_b nearest linked
+ *               references (by (distance, id)); 0 keeps all.
+ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(ann_build_params) */
+    int32_t graph_k;
+    int32_t P;
+    int32_t K;
+    int32_t kmeans_iters;
+    int32_t bridge_t;
+    int32_t bridge_b;
+    int32_t reserved; /* must be 0 */
+    uint64_t seed;
+} ann_build_params;
+
+/*
+ * Search parameters (Alg. 1).
+ *  queue_len  L, capacity of the main queue of reference vectors
+ *             (1 <= L <= 64).  When the queue is full a new candidate
+ *             evicts the worst entry if it is better, else it is dropped
+ *             (it stays visited and in the result set).  The single bridge
+ *             vector of the paper's main queue is held in its own slot.
+ *  precision  ann_precision (ignored for u8).
+ *  rerank_k   ANN_PRECISION_BF16_RERANK only: how many of the best bf16
+ *             candidates are re-ranked in fp32 (0 means k).
+ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(ann_search_params) */
+    int32_t queue_len;
+    int32_t precision;
+    int32_t rerank_k;
+} ann_search_params;
+
+typedef struct {
+    int64_t n;                /* reference vectors */
+    int32_t d;                /* dimension */
+    int32_t dtype;            /* ann_dtype */
+    int32_t P, K;             /* subspaces, codewords per subspace */
+    int32_t graph_k;          /* R */
+    int32_t reserved;
+    int64_t n_bridges;        /* K^P */
+    int64_t n_bridge_entries; /* E, total length of all bridge lists */
+    int64_t device_bytes;     /* device memory owned by the index */
+} ann_index_info;
+
+/* Per-query counters written by ann_search_device when d_stats is given
+ * (nq x ANN_NSTATS int32, row-major). */
+enum {
+    ANN_STAT_EVALS = 0,        /* distance evaluations t (<= budget) */
+    ANN_STAT_REF_POPS = 1,     /* reference vectors expanded (kNN rows read) */
+    ANN_STAT_BRIDGE_POPS = 2,  /* non-empty bridge vectors expanded */
+    ANN_STAT_BRIDGE_IDS = 3,   /* bridge-list entries read */
+    ANN_STAT_BRIDGES_GEN = 4,  /* bridges extracted by the multi-sequence,
+                                  empty ones and look-ahead included */
+    ANN_STAT_HEAP_MAX = 5,     /* largest multi-sequence frontier */
+    ANN_STAT_FLAGS = 6,        /* 0, or ANN_ERESOURCE if a structure overflowed */
+    ANN_STAT_RESERVED = 7,
+    ANN_NSTATS = 8
+};
+
+/* ------------------------------------------------------------------ */
+/* Index construction                                                  */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Build the index on the current HIP device (Sec. 4.1): copy X to the
+ * device, train the codebooks (k-means per subspace), build the exact kNN
+ * graph and the bridge graph.
+ *  data       host, n x d row-major, uint8 (ANN_U8) or float (ANN_F32).
+ *  codebooks  host, optional: P x K x (d/P) of the data dtype.  When given
+ *             no k-means runs and these codewords are used as they are.
+ *  graph      host, optional: n x graph_k uint32 kNN rows to use instead of
+ *             building them (each row: ids in [0, n), no repeats).
+ *  out        receives the new index; free it with ann_index_free.
+ * Errors: ANN_EINVAL (null data/out/params, n < 1, d < 1, P does not divide
+ * d, K out of range, K > n when training, n + K^P >= 2^32, bridge_t < 1,
+ * bridge_b < 0, graph_k < 0 or >= n, u8 rows not a multiple of 16 bytes,
+ * f32 d not a multiple of 4), ANN_ENOMEM, ANN_EDEVICE.
+ */
+int ann_build_index(const void* data, int64_t n, int32_t d, int32_t dtype, const ann_build_params* params,
+                    const void* codebooks, const uint32_t* graph, ann_index** out);
+
+/*
+ * Assemble an index from given parts (host arrays) without building any of
+ * them; used to search an index built elsewhere.
+ *  data        n x d (dtype); codebooks P x K x (d/P) (dtype);
+ *  graph       n x graph_k uint32 (may be null when graph_k == 0);
+ *  bridge_off  K^P + 1 uint32 offsets, bridge_off[0] = 0, non-decreasing;
+ *  bridge_ids  bridge_off[K^P] uint32 reference ids; list lid is
+ *              bridge_ids[bridge_off[lid] .. bridge_off[lid+1]).
+ * Lists and graph rows must not repeat an id.
+ * Errors: ANN_EINVAL on inconsistent sizes or ids out of range.
+ */
+int ann_index_import(const void* data, int64_t n, int32_t d, int32_t dtype, int32_t P, int32_t K,
+                     const void* codebooks, int32_t graph_k, const uint32_t* graph, const uint32_t* bridge_off,
+                     const uint32_t* bridge_ids, ann_index** out);
+
+int ann_index_get_info(const ann_index* idx, ann_index_info* info);
+
+/*
+ * Copy index parts to host buffers sized from ann_index_get_info; each
+ * pointer may be null to skip that part.  codebooks P x K x (d/P) (dtype),
+ * graph n x graph_k, bridge_off K^P + 1, bridge_ids n_bridge_entries.
+ */
+int ann_index_export(const ann_index* idx, void* codebooks, uint32_t* graph, uint32_t* bridge_off,
+                     uint32_t* bridge_ids);
+
+/* Write / read a versioned binary file holding the whole index. */
+int ann_index_save(const ann_index* idx, const char* path);
+int ann_index_load(const char* path, ann_index** out);
+
+void ann_index_free(ann_index* idx);
+
+/* ------------------------------------------------------------------ */
+/* Search (Sec. 4.2, Alg. 1)                                           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Best-first search over the augmented graph for nq queries.
+ * For each query: subspace distance tables and their sort, multi-sequence
+ * extraction of bridge vectors in increasing distance, then Alg. 1 with a
+ * strict budget of `budget` distance evaluations.
+ *  queries  host, nq x d (index dtype).
+ *  k        1..1024 results per query; budget >= 0.
+ *  ids      host, nq x k int32.  dists host, nq x k (int32 for u8, float
+ *           for f32).
+ * Synchronous.  Errors: ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ERESOURCE.
+ */
+int ann_search(const ann_index* idx, const void* queries, int64_t nq, int32_t k, int32_t budget,
+               const ann_search_params* params, int32_t* ids, void* dists);
+
+/*
+ * Device form of ann_search, asynchronous on `stream` (a hipStream_t, may
+ * be null for the default stream).  All buffers are device memory.
+ *  d_k, d_budget  optional per-query k and budget (int32, nq each); when
+ *                 given, each entry must lie in [1, k] and [0, budget].
+ *                 k and budget are then the maxima: row stride of the
+ *                 outputs and the size of per-query structures.
+ *  d_ids, d_dists nq x k outputs (row stride k).
+ *  d_stats        optional nq x ANN_NSTATS int32 counters.
+ *  d_trace        optional nq x budget int32: the ids in evaluation order,
+ *                 padded with -1.
+ * A query whose multi-sequence frontier outgrows its capacity gets flag
+ * ANN_ERESOURCE in d_stats and a row of -1; ann_search reports it as an
+ * error.
+ */
+int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                      const int32_t* d_k, const int32_t* d_budget, const ann_search_params* params,
+                      int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
+
+/*
+ * Query preprocessing alone (Sec. 4.2): for each query the P x K squared
+ * distances to the codewords, each subspace sorted ascending by
+ * (value, codeword index).  d_sorted nq x P x K (int32 for u8, float for
+ * f32); d_perm nq x P x K int32 codeword of each rank.  Asynchronous.
+ */
+int ann_query_tables_device(const ann_index* idx, const void* d_queries, int64_t nq, void* d_sorted,
+                            int32_t* d_perm, void* stream);
+
+/*
+ * Exact k nearest neighbours by linear scan (the ground truth of Sec. 5.1).
+ *  d_x n x d, d_q nq x d (dtype); exclude_self != 0 means query i is row i
+ *  of d_x and is left out of its own list (the kNN graph).  Outputs nq x k
+ *  ascending by (distance, id).  Asynchronous.
+ */
+int ann_knn_device(const void* d_x, int64_t n, int32_t d, int32_t dtype, const void* d_q, int64_t nq, int32_t k,
+                   int32_t exclude_self, int32_t* d_ids, void* d_dists, void* stream);
+
+/* Thread-local message of the last error; never null. */
+const char* ann_last_error(void);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int ann_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANN_H */

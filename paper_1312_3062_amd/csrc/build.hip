@@ -1,0 +1,456 @@
+// Index build on the GPU (Sec. 4.1): product-quantisation codebooks by
+// k-means per subspace, and the bridge graph linking bridge vectors
+// (Cartesian concatenations of codewords) to reference vectors.
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "internal.hpp"
+#include "mseq.hpp"
+
+namespace ann {
+
+// ----------------------------------------------------------------------
+// SplitMix64 (Steele, Lea and Flood, 2014): add the golden-ratio increment,
+// then two xor-shift-multiply rounds and a final xor-shift.
+// ----------------------------------------------------------------------
+static uint64_t splitmix64(uint64_t& state) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// First K positions of a Fisher-Yates shuffle of [0, n): the initial rows.
+void kmeans_init_rows(int64_t n, int K, uint64_t seed, int64_t* rows) {
+    std::vector<std::pair<int64_t, int64_t>> moved;  // (position, value) writes, latest last
+    auto value_at = [&](int64_t i) {
+        for (auto it = moved.rbegin(); it != moved.rend(); ++it)
+            if (it->first == i) return it->second;
+        return i;
+    };
+    uint64_t st = seed;
+    for (int i = 0; i < K; ++i) {
+        const int64_t j = i + int64_t(splitmix64(st) % uint64_t(n - i));
+        const int64_t vi = value_at(i), vj = value_at(j);
+        moved.emplace_back(i, vj);
+        moved.emplace_back(j, vi);
+        rows[i] = vj;
+    }
+}
+
+namespace {
+
+constexpr int KM_THREADS = 256;
+
+// ----------------------------------------------------------------------
+// k-means assignment + per-workgroup partial sums.  One thread per point,
+// all subspaces; centroids of every subspace cached in LDS.
+//   u8: nearest by |x|^2 - 2 x.c + |c|^2 (exact ints), ties to smaller j;
+//       member sums exact in uint64.
+//   f32: nearest by fp32 sum (x - c)^2; sums in int64 fixed point
+//       (x * 2^scale_log2 rounded), so the reduction order does not matter.
+// ----------------------------------------------------------------------
+// per-workgroup member sums: 256 bytes fit uint32; f32 fixed point needs 64 bits
+template <bool FLOAT>
+using lsum_t = typename std::conditional<FLOAT, unsigned long long, unsigned int>::type;
+
+template <bool FLOAT>
+__host__ __device__ inline int kmeans_lds_bytes(int P, int K, int ds) {
+    const int PKd = P * K * ds;
+    return ((PKd * (FLOAT ? 4 : 1) + 15) & ~15) + ((P * K * 4 + 15) & ~15) +
+           ((PKd * int(sizeof(lsum_t<FLOAT>)) + 15) & ~15) + P * K * 4;
+}
+
+template <bool FLOAT>
+__global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, int64_t n, int d, int P, int K,
+                                                               const void* cb, uint64_t* sums, uint32_t* counts,
+                                                               int32_t* assign, float fx_scale) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int ds = d / P;
+    const int esz = FLOAT ? 4 : 1;
+    const int PKd0 = P * K * ds;
+    uint8_t* c_l = lds;                                                   // P*K*ds elements
+    const int cbytes = (PKd0 * esz + 15) & ~15;
+    uint32_t* cnorm = reinterpret_cast<uint32_t*>(lds + cbytes);        // P*K (u8)
+    lsum_t<FLOAT>* lsum = reinterpret_cast<lsum_t<FLOAT>*>(lds + cbytes + ((P * K * 4 + 15) & ~15));  // P*K*ds
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(lsum) +
+                                                 ((PKd0 * int(sizeof(lsum_t<FLOAT>)) + 15) & ~15));  // P*K
+    const int PKd = P * K * ds;
+    for (int i = threadIdx.x; i < PKd * esz / 4; i += KM_THREADS)
+        reinterpret_cast<uint32_t*>(c_l)[i] = static_cast<const uint32_t*>(cb)[i];
+    for (int i = threadIdx.x; i < PKd; i += KM_THREADS) lsum[i] = 0;
+    for (int i = threadIdx.x; i < P * K; i += KM_THREADS) lcnt[i] = 0;
+    __syncthreads();
+    if constexpr (!FLOAT) {
+        for (int e = threadIdx.x; e < P * K; e += KM_THREADS) {
+            uint32_t s = 0;
+            for (int i = 0; i < ds; ++i) s += uint32_t(c_l[e * ds + i]) * c_l[e * ds + i];
+            cnorm[e] = s;
+        }
+        __syncthreads();
+    }
+    const int64_t i = int64_t(blockIdx.x) * KM_THREADS + threadIdx.x;
+    if (i < n) {
+        for (int p = 0; p < P; ++p) {
+            int best = 0;
+            uint32_t bd = 0;
+            for (int j = 0; j < K; ++j) {
+                uint32_t dist;
+                if constexpr (!FLOAT) {
+                    const uint8_t* x = X + i * d + p * ds;
+                    const uint8_t* c = c_l + (p * K + j) * ds;
+                    uint32_t dot = 0;
+                    int e = 0;
+                    if ((ds & 3) == 0) {
+                        for (; e < ds; e += 4) {
+                            uint32_t xw, cw;
+                            __builtin_memcpy(&xw, x + e, 4);
+                            __builtin_memcpy(&cw, c + e, 4);
+                            dot = __builtin_amdgcn_udot4(xw, cw, dot, false);
+                        }
+                    }
+                    for (; e < ds; ++e) dot += uint32_t(x[e]) * c[e];
+                    dist = cnorm[p * K + j] - 2u * dot;  // |x|^2 is common to all j
+                    dist += 0x80000000u;                  // order-preserving bias (value may be negative)
+                } else {
+                    const float* x = reinterpret_cast<const float*>(X) + i * d + p * ds;
+                    const float* c = reinterpret_cast<const float*>(c_l) + (p * K + j) * ds;
+                    float acc = 0.f;
+                    for (int e = 0; e < ds; ++e) {
+                        const float t = x[e] - c[e];
+                        acc = fmaf(t, t, acc);
+                    }
+                    dist = __float_as_uint(acc);
+                }
+                if (j == 0 || dist < bd) {
+                    bd = dist;
+                    best = j;
+                }
+            }
+            if (assign) assign[i * P + p] = best;
+            atomicAdd(&lcnt[p * K + best], 1u);
+            for (int e = 0; e < ds; ++e) {
+                lsum_t<FLOAT> v;
+                if constexpr (!FLOAT)
+                    v = X[i * d + p * ds + e];
+                else
+                    v = static_cast<unsigned long long>(
+                        __float2ll_rn(reinterpret_cast<const float*>(X)[i * d + p * ds + e] * fx_scale));
+                atomicAdd(&lsum[(p * K + best) * ds + e], v);
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < PKd; e += KM_THREADS)
+        if (lsum[e]) atomicAdd(reinterpret_cast<unsigned long long*>(&sums[e]), static_cast<unsigned long long>(lsum[e]));
+    for (int e = threadIdx.x; e < P * K; e += KM_THREADS)
+        if (lcnt[e]) atomicAdd(&counts[e], lcnt[e]);
+}
+
+// update: member mean, u8 rounded half up in exact integers; empty keeps
+template <bool FLOAT>
+__global__ void k_kmeans_update(void* cb, const uint64_t* sums, const uint32_t* counts, int P, int K, int ds,
+                                float inv_fx_scale) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= P * K * ds) return;
+    const uint32_t cnt = counts[e / ds];
+    if (cnt == 0) return;
+    if constexpr (!FLOAT) {
+        const uint64_t s = sums[e];
+        static_cast<uint8_t*>(cb)[e] = uint8_t((2 * s + cnt) / (2 * uint64_t(cnt)));
+    } else {
+        const int64_t s = int64_t(sums[e]);
+        static_cast<float*>(cb)[e] = float(s) * inv_fx_scale / float(cnt);
+    }
+}
+
+// ----------------------------------------------------------------------
+// Bridge graph, step 1: for every reference vector its top-t bridges by
+// (distance, lid), from the reference's own subspace tables and the
+// multi-sequence heap.  One wavefront per reference vector.
+// Output key = (distance bits << 32 | reference id), lid alongside.
+// ----------------------------------------------------------------------
+__host__ __device__ inline int topt_layout(int rowb, int PK, int heap_cap, int& o_tab, int& o_sv, int& o_hk,
+                                           int& o_hr, int& o_perm) {
+    o_tab = (rowb + 15) & ~15;
+    o_sv = o_tab + PK * 4;
+    o_hk = (o_sv + PK * 4 + 7) & ~7;
+    o_hr = o_hk + heap_cap * 8;
+    o_perm = o_hr + heap_cap * 4;
+    return (o_perm + PK + 15) & ~15;
+}
+
+template <bool FLOAT>
+__global__ void __launch_bounds__(WAVE) k_bridge_topt(const uint8_t* X, int64_t n, int d, int P, int K,
+                                                       const void* cb, int t, int heap_cap, uint32_t* out_lid,
+                                                       uint64_t* out_key, uint32_t* counts) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int ds = d / P;
+    const int PK = P * K;
+    const int rowb = FLOAT ? d * 4 : d;
+    int o_tab, o_sv, o_hk, o_hr, o_perm;
+    topt_layout(rowb, PK, heap_cap, o_tab, o_sv, o_hk, o_hr, o_perm);
+    uint8_t* qv = lds;
+    uint32_t* tab = reinterpret_cast<uint32_t*>(lds + o_tab);
+    uint32_t* sv = reinterpret_cast<uint32_t*>(lds + o_sv);
+    uint64_t* hk = reinterpret_cast<uint64_t*>(lds + o_hk);
+    uint32_t* hr = reinterpret_cast<uint32_t*>(lds + o_hr);
+    uint8_t* perm = lds + o_perm;
+    const int lane = lane_id();
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        for (int w = lane; w < rowb / 4; w += WAVE)
+            reinterpret_cast<uint32_t*>(qv)[w] = reinterpret_cast<const uint32_t*>(X + i * rowb)[w];
+        __syncthreads();
+        compute_tables<FLOAT>(qv, cb, P, K, ds, tab, sv, perm, lane);
+        if (lane == 0) {
+            // keys carry n + lid like the search; strip n when writing
+            int hn = 0;
+            heap_push(hk, hr, hn, tuple_key<FLOAT>(0u, sv, perm, P, K, 0), 0u);
+            for (int j = 0; j < t; ++j) {
+                uint64_t key;
+                uint32_t rk;
+                heap_pop(hk, hr, hn, key, rk);
+                out_lid[i * t + j] = key_id(key);
+                out_key[i * t + j] = make_key(key_dist(key), uint32_t(i));
+                atomicAdd(&counts[key_id(key)], 1u);
+                int last = 0;
+                for (int p = 0; p < P; ++p)
+                    if ((rk >> (8 * p)) & 0xFF) last = p;
+                for (int b = last; b < P; ++b) {
+                    const int r = (rk >> (8 * b)) & 0xFF;
+                    if (r + 1 >= K) continue;
+                    const uint32_t crk = rk + (1u << (8 * b));
+                    heap_push(hk, hr, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, 0), crk);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// step 2: scatter each (bridge, key) into its bridge's bucket
+__global__ void k_bridge_scatter(const uint32_t* lid, const uint64_t* key, int64_t m, const uint32_t* start,
+                                 uint32_t* cursor, uint64_t* bucket) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const uint32_t b = lid[i];
+    const uint32_t pos = start[b] + atomicAdd(&cursor[b], 1u);
+    bucket[pos] = key[i];
+}
+
+// step 3: order each bucket by (distance, id); keep the first b (0 = all)
+__global__ void k_bridge_sort(uint64_t* bucket, const uint32_t* start, const uint32_t* count, int64_t nb, int b,
+                              uint32_t* kept) {
+    const int64_t lid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (lid >= nb) return;
+    uint64_t* v = bucket + start[lid];
+    const int m = int(count[lid]);
+    const int keep = (b > 0 && b < m) ? b : m;
+    // selection of the `keep` smallest, in order (in place)
+    for (int i = 0; i < keep; ++i) {
+        int best = i;
+        uint64_t bv = v[i];
+        for (int j = i + 1; j < m; ++j) {
+            const uint64_t x = v[j];
+            if (x < bv) {
+                bv = x;
+                best = j;
+            }
+        }
+        v[best] = v[i];
+        v[i] = bv;
+    }
+    kept[lid] = uint32_t(keep);
+}
+
+// step 4: CSR ids
+__global__ void k_bridge_emit(const uint64_t* bucket, const uint32_t* start, const uint32_t* off, int64_t nb,
+                              uint32_t* ids) {
+    const int64_t lid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (lid >= nb) return;
+    const uint32_t o = off[lid], e = off[lid + 1], s = start[lid];
+    for (uint32_t i = 0; i < e - o; ++i) ids[o + i] = key_id(bucket[s + i]);
+}
+
+// ----------------------------------------------------------------------
+// exclusive scan of uint32 counts (n + 1 outputs, last = total)
+// ----------------------------------------------------------------------
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ void k_scan_block(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* block_sums) {
+    __shared__ uint32_t s[SCAN_BLOCK];
+    const int64_t i = int64_t(blockIdx.x) * SCAN_BLOCK + threadIdx.x;
+    const uint32_t v = i < n ? in[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < SCAN_BLOCK; o <<= 1) {
+        const uint32_t add = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0;
+        __syncthreads();
+        s[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (i < n) out[i] = s[threadIdx.x] - v;  // exclusive
+    if (threadIdx.x == SCAN_BLOCK - 1) block_sums[blockIdx.x] = s[threadIdx.x];
+}
+
+__global__ void k_scan_sums(uint32_t* block_sums, int64_t nblocks, uint32_t* total) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int64_t b = 0; b < nblocks; ++b) {
+        const uint32_t v = block_sums[b];
+        block_sums[b] = run;
+        run += v;
+    }
+    *total = run;
+}
+
+__global__ void k_scan_add(uint32_t* out, int64_t n, const uint32_t* block_sums) {
+    const int64_t i = int64_t(blockIdx.x) * SCAN_BLOCK + threadIdx.x;
+    if (i < n) out[i] += block_sums[blockIdx.x];
+}
+
+int exclusive_scan(const uint32_t* in, int64_t n, uint32_t* out /* n + 1 */, hipStream_t s) {
+    const int64_t nbk = ceil_div(n, SCAN_BLOCK);
+    uint32_t* bs = nullptr;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&bs), size_t(nbk) * 4, s));
+    hipLaunchKernelGGL(k_scan_block, dim3(unsigned(nbk)), dim3(SCAN_BLOCK), 0, s, in, n, out, bs);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, bs, nbk, out + n);
+    hipLaunchKernelGGL(k_scan_add, dim3(unsigned(nbk)), dim3(SCAN_BLOCK), 0, s, out, n, bs);
+    ANN_HIP_CHECK(hipGetLastError());
+    ANN_HIP_CHECK(hipFreeAsync(bs, s));
+    return ANN_OK;
+}
+
+__global__ void k_to_bf16(const float* x, int64_t m, uint16_t* y) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < m) y[i] = f32_to_bf16_rne(x[i]);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------
+// host orchestration
+// ----------------------------------------------------------------------
+int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
+    // the initial codewords are already in idx->codebooks
+    const bool f = idx->dtype == ANN_F32;
+    const int P = idx->P, K = idx->K, ds = idx->d / idx->P;
+    const int PKd = P * K * ds;
+    uint64_t* sums = nullptr;
+    uint32_t* counts = nullptr;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&sums), size_t(PKd) * 8, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&counts), size_t(P * K) * 4, s));
+    // f32 sums in fixed point x * 2^fx_log2 (the caller bounds n * max|x| * 2^fx_log2 by 2^62)
+    const float fx = f ? ldexpf(1.f, fx_log2) : 1.f;
+    const float inv_fx = f ? ldexpf(1.f, -fx_log2) : 1.f;
+    const int lds = f ? kmeans_lds_bytes<true>(P, K, ds) : kmeans_lds_bytes<false>(P, K, ds);
+    int dev = 0, max_lds = 0;
+    ANN_HIP_CHECK(hipGetDevice(&dev));
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (lds > max_lds) return set_error(ANN_EUNSUPPORTED, "codebooks too large for the k-means kernel");
+    const int64_t grid = ceil_div(idx->n, KM_THREADS);
+    for (int it = 0; it < iters; ++it) {
+        ANN_HIP_CHECK(hipMemsetAsync(sums, 0, size_t(PKd) * 8, s));
+        ANN_HIP_CHECK(hipMemsetAsync(counts, 0, size_t(P * K) * 4, s));
+        if (f)
+            hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds, s, idx->X, idx->n,
+                               idx->d, P, K, idx->codebooks, sums, counts, nullptr, fx);
+        else
+            hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds, s, idx->X,
+                               idx->n, idx->d, P, K, idx->codebooks, sums, counts, nullptr, fx);
+        ANN_HIP_CHECK(hipGetLastError());
+        const int ub = (PKd + 255) / 256;
+        if (f)
+            hipLaunchKernelGGL(k_kmeans_update<true>, dim3(ub), dim3(256), 0, s, idx->codebooks, sums, counts, P, K,
+                               ds, inv_fx);
+        else
+            hipLaunchKernelGGL(k_kmeans_update<false>, dim3(ub), dim3(256), 0, s, idx->codebooks, sums, counts, P,
+                               K, ds, inv_fx);
+        ANN_HIP_CHECK(hipGetLastError());
+    }
+    ANN_HIP_CHECK(hipFreeAsync(sums, s));
+    ANN_HIP_CHECK(hipFreeAsync(counts, s));
+    return ANN_OK;
+}
+
+int build_bridge_graph(ann_index* idx, int t, int b, hipStream_t s) {
+    const bool f = idx->dtype == ANN_F32;
+    const int64_t n = idx->n, nb = idx->nb;
+    if (t > nb) t = int(nb);
+    const int64_t m = n * t;
+    if (m >= (int64_t(1) << 32)) return set_error(ANN_EUNSUPPORTED, "n * bridge_t must stay below 2^32");
+    uint32_t *lid = nullptr, *counts = nullptr, *start = nullptr, *cursor = nullptr, *kept = nullptr;
+    uint64_t *key = nullptr, *bucket = nullptr;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&lid), size_t(m) * 4, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&key), size_t(m) * 8, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&counts), size_t(nb) * 4, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&start), size_t(nb + 1) * 4, s));
+    ANN_HIP_CHECK(hipMemsetAsync(counts, 0, size_t(nb) * 4, s));
+
+    const int heap_cap = 1 + (idx->P - 1) * t + idx->P;
+    const int rowb = f ? idx->d * 4 : idx->d;
+    const int PK = idx->P * idx->K;
+    int o1, o2, o3, o4, o5;
+    const int lds = topt_layout(rowb, PK, heap_cap, o1, o2, o3, o4, o5);
+    int dev = 0, max_lds = 0;
+    ANN_HIP_CHECK(hipGetDevice(&dev));
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (lds > max_lds) return set_error(ANN_EUNSUPPORTED, "bridge_t too large for the bridge-graph kernel");
+    const int64_t grid = std::min<int64_t>(n, 1 << 20);
+    if (f)
+        hipLaunchKernelGGL(k_bridge_topt<true>, dim3(unsigned(grid)), dim3(WAVE), lds, s, idx->X, n, idx->d, idx->P,
+                           idx->K, idx->codebooks, t, heap_cap, lid, key, counts);
+    else
+        hipLaunchKernelGGL(k_bridge_topt<false>, dim3(unsigned(grid)), dim3(WAVE), lds, s, idx->X, n, idx->d,
+                           idx->P, idx->K, idx->codebooks, t, heap_cap, lid, key, counts);
+    ANN_HIP_CHECK(hipGetLastError());
+    int rc = exclusive_scan(counts, nb, start, s);
+    if (rc) return rc;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&cursor), size_t(nb) * 4, s));
+    ANN_HIP_CHECK(hipMemsetAsync(cursor, 0, size_t(nb) * 4, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&bucket), size_t(m) * 8, s));
+    hipLaunchKernelGGL(k_bridge_scatter, dim3(unsigned(ceil_div(m, 256))), dim3(256), 0, s, lid, key, m, start,
+                       cursor, bucket);
+    ANN_HIP_CHECK(hipGetLastError());
+    ANN_HIP_CHECK(hipFreeAsync(lid, s));
+    ANN_HIP_CHECK(hipFreeAsync(key, s));
+    ANN_HIP_CHECK(hipFreeAsync(cursor, s));
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&kept), size_t(nb) * 4, s));
+    hipLaunchKernelGGL(k_bridge_sort, dim3(unsigned(ceil_div(nb, 256))), dim3(256), 0, s, bucket, start, counts, nb,
+                       b, kept);
+    ANN_HIP_CHECK(hipGetLastError());
+    int rc2 = dalloc(idx, reinterpret_cast<void**>(&idx->boff), size_t(nb + 1) * 4);
+    if (rc2) return rc2;
+    rc = exclusive_scan(kept, nb, idx->boff, s);
+    if (rc) return rc;
+    uint32_t E = 0;
+    ANN_HIP_CHECK(hipMemcpyAsync(&E, idx->boff + nb, 4, hipMemcpyDeviceToHost, s));
+    ANN_HIP_CHECK(hipStreamSynchronize(s));
+    idx->E = E;
+    rc2 = dalloc(idx, reinterpret_cast<void**>(&idx->bids), size_t(std::max<int64_t>(E, 1)) * 4);
+    if (rc2) return rc2;
+    hipLaunchKernelGGL(k_bridge_emit, dim3(unsigned(ceil_div(nb, 256))), dim3(256), 0, s, bucket, start, idx->boff,
+                       nb, idx->bids);
+    ANN_HIP_CHECK(hipGetLastError());
+    ANN_HIP_CHECK(hipFreeAsync(bucket, s));
+    ANN_HIP_CHECK(hipFreeAsync(counts, s));
+    ANN_HIP_CHECK(hipFreeAsync(start, s));
+    ANN_HIP_CHECK(hipFreeAsync(kept, s));
+    ANN_HIP_CHECK(hipStreamSynchronize(s));
+    return ANN_OK;
+}
+
+int make_bf16_copy(ann_index* idx, hipStream_t s) {
+    if (idx->dtype != ANN_F32 || idx->Xbf16) return ANN_OK;
+    const int64_t m = idx->n * idx->d;
+    int rc = dalloc(idx, reinterpret_cast<void**>(&idx->Xbf16), size_t(m) * 2);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_to_bf16, dim3(unsigned(ceil_div(m, 256))), dim3(256), 0, s,
+                       reinterpret_cast<const float*>(idx->X), m, idx->Xbf16);
+    ANN_HIP_CHECK(hipGetLastError());
+    return ANN_OK;
+}
+
+}  // namespace ann

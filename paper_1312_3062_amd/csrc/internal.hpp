@@ -1,0 +1,58 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include "common.hpp"
+
+struct ann_index {
+    int64_t n = 0;
+    int32_t d = 0;
+    int32_t dtype = 0;
+    int32_t P = 0, K = 0, R = 0;
+    int64_t nb = 0;  // K^P bridge vectors
+    int64_t E = 0;   // total length of the bridge lists
+    int device = 0;
+    int64_t row_bytes = 0;  // d (u8) or 4d (f32)
+    uint8_t* X = nullptr;           // n x row_bytes
+    uint16_t* Xbf16 = nullptr;      // n x d bf16 copy (f32 indexes, made on first use)
+    void* codebooks = nullptr;      // P x K x (d/P), dtype of X
+    uint32_t* G = nullptr;          // n x R
+    uint32_t* boff = nullptr;       // nb + 1
+    uint32_t* bids = nullptr;       // E
+    int64_t bytes = 0;
+};
+
+namespace ann {
+
+struct SearchLaunch {
+    const ann_index* idx;
+    const void* d_q;
+    int64_t nq;
+    int kmax, Tmax;
+    const int32_t* d_k;
+    const int32_t* d_T;
+    int L;
+    int precision;
+    int rerank_k;
+    int32_t* d_ids;
+    void* d_dists;
+    int32_t* d_stats;
+    int32_t* d_trace;
+    hipStream_t stream;
+};
+
+int launch_search(const SearchLaunch& a);
+int launch_tables(const ann_index* idx, const void* d_q, int64_t nq, void* d_sorted, int32_t* d_perm,
+                  hipStream_t s);
+int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, int64_t nq, int k, int exclude_self,
+               int32_t* d_ids, void* d_dists, hipStream_t s);
+int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s);
+int build_bridge_graph(ann_index* idx, int t, int b, hipStream_t s);
+int make_bf16_copy(ann_index* idx, hipStream_t s);
+
+// SplitMix64 and the seeded choice of the initial k-means rows (host side).
+void kmeans_init_rows(int64_t n, int K, uint64_t seed, int64_t* rows);
+
+// Device allocation tracked in the index's byte count.
+int dalloc(ann_index* idx, void** p, size_t bytes);
+
+}  // namespace ann

@@ -1,0 +1,237 @@
+"""GPU vs oracle parity through the C ABI.
+
+u8 results must be bit-exact: codebooks, kNN graph, bridge CSR, returned ids,
+int32 distances and the evaluation order.  Sizes are chosen so that the
+oracle finishes in seconds while the kernels still run many tiles, chunks
+and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1312_3062_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _index_cls():
+    from paper_1312_3062_amd import Index
+    return Index
+
+
+def gpu_search(idx, Q, k, T, L=64, ks=None, Ts=None, trace=False, stats=False, precision=0, rerank_k=0):
+    qd = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
+    nq = Q.shape[0]
+    tr = torch.empty((nq, max(T, 1)), dtype=torch.int32, device="cuda") if trace else None
+    st = torch.empty((nq, 8), dtype=torch.int32, device="cuda") if stats else None
+    kd = None if ks is None else torch.from_numpy(np.asarray(ks, np.int32)).cuda()
+    td = None if Ts is None else torch.from_numpy(np.asarray(Ts, np.int32)).cuda()
+    ids, dd = _index_cls().search_device(idx, qd, k, T, ks=kd, budgets=td, queue_len=L, trace=tr, stats=st,
+                                         precision=precision, rerank_k=rerank_k)
+    torch.cuda.synchronize()
+    out = [ids.cpu().numpy(), dd.cpu().numpy()]
+    if trace:
+        out.append(tr.cpu().numpy())
+    if stats:
+        out.append(st.cpu().numpy())
+    return out
+
+
+def assert_search_equal(idx, parts, X, Q, k, T, L, **kw):
+    gi, gd, gt = gpu_search(idx, Q, k, T, L, trace=True, **kw)
+    ks = kw.get("ks", k)
+    Ts = kw.get("Ts", T)
+    oi, od, ot = oracle.search(X, parts["codebooks"], parts["graph"], parts["bridge_off"], parts["bridge_ids"], Q,
+                               ks, Ts, L, trace_len=max(T, 1))
+    np.testing.assert_array_equal(gi, oi)
+    np.testing.assert_array_equal(gd.astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
+    if T > 0:
+        np.testing.assert_array_equal(gt, ot)
+
+
+# ---------------------------------------------------------------- the 10K x 128 u8 workload, in full
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = synth.WORKLOADS["tiny_10k_u8"]
+    X = synth.base_vectors(w)
+    Q = synth.queries(w)
+    idx = _index_cls().build(X, w.graph_k, w.P, w.K, w.kmeans_iters, w.kmeans_seed, w.bridge_t, w.bridge_b)
+    parts = idx.export()
+    return dict(w=w, X=X, Q=Q, idx=idx, parts=parts)
+
+
+@pytest.fixture(scope="module")
+def tiny_oracle(tiny):
+    w, X = tiny["w"], tiny["X"]
+    cb = oracle.kmeans(X, w.P, w.K, w.kmeans_iters, w.kmeans_seed)
+    g, _ = oracle.knn_graph_rows(X, np.arange(len(X)), w.graph_k)
+    off, ids, _ = oracle.bridge_graph(X, cb, w.bridge_t, w.bridge_b)
+    return dict(codebooks=cb, graph=g.astype(np.uint32), bridge_off=off, bridge_ids=ids)
+
+
+def test_tiny_codebooks_bit_exact(tiny, tiny_oracle):
+    np.testing.assert_array_equal(tiny["parts"]["codebooks"], tiny_oracle["codebooks"])
+
+
+def test_tiny_knn_graph_bit_exact(tiny, tiny_oracle):
+    np.testing.assert_array_equal(tiny["parts"]["graph"], tiny_oracle["graph"])
+
+
+def test_tiny_bridge_csr_bit_exact(tiny, tiny_oracle):
+    np.testing.assert_array_equal(tiny["parts"]["bridge_off"], tiny_oracle["bridge_off"])
+    np.testing.assert_array_equal(tiny["parts"]["bridge_ids"], tiny_oracle["bridge_ids"])
+
+
+def test_tiny_search_bit_exact(tiny):
+    w = tiny["w"]
+    assert_search_equal(tiny["idx"], tiny["parts"], tiny["X"], tiny["Q"], w.k, 256, w.queue_len)
+
+
+@pytest.mark.parametrize("k,T,L", [(1, 0, 64), (10, 1, 64), (10, 17, 1), (100, 300, 7), (5, 1000, 64),
+                                   (33, 129, 2), (1, 64, 64)])
+def test_tiny_search_budget_grid(tiny, k, T, L):
+    Q = tiny["Q"][:40]
+    assert_search_equal(tiny["idx"], tiny["parts"], tiny["X"], Q, k, T, L)
+
+
+def test_tiny_per_query_k_and_budget(tiny):
+    rng = np.random.default_rng(0)
+    Q = tiny["Q"]
+    ks = rng.choice([1, 10, 100], size=len(Q)).astype(np.int32)
+    Ts = rng.integers(0, 700, size=len(Q)).astype(np.int32)
+    assert_search_equal(tiny["idx"], tiny["parts"], tiny["X"], Q, 100, 700, 64, ks=ks, Ts=Ts)
+
+
+def test_tiny_stats_are_consistent(tiny):
+    Q = tiny["Q"]
+    gi, gd, st = gpu_search(tiny["idx"], Q, 10, 256, 64, stats=True)
+    assert (st[:, 0] <= 256).all() and (st[:, 6] == 0).all()
+    _, _, _, ost = oracle.search(tiny["X"], tiny["parts"]["codebooks"], tiny["parts"]["graph"],
+                                 tiny["parts"]["bridge_off"], tiny["parts"]["bridge_ids"], Q, 10, 256, 64,
+                                 trace_len=1, stats=True)
+    np.testing.assert_array_equal(st[:, 0], ost[:, 0])   # evaluations
+    np.testing.assert_array_equal(st[:, 1], ost[:, 1])   # reference pops
+
+
+def test_tiny_tables_bit_exact(tiny):
+    Q = tiny["Q"][:20]
+    sv, perm = tiny["idx"].tables_device(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    sv, perm = sv.cpu().numpy(), perm.cpu().numpy()
+    for i in range(len(Q)):
+        tab = oracle.tables(Q[i], tiny["parts"]["codebooks"])
+        op, osv = oracle.sort_tables(tab)
+        np.testing.assert_array_equal(perm[i], op)
+        np.testing.assert_array_equal(sv[i].astype(np.float64), osv)
+
+
+def test_knn_device_matches_oracle(tiny):
+    from paper_1312_3062_amd import knn_device
+    X, Q = tiny["X"], tiny["Q"]
+    xd = torch.from_numpy(X).cuda()
+    qd = torch.from_numpy(Q).cuda()
+    for k in (1, 10, 32):
+        ids, dd = knn_device(xd, qd, k)
+        torch.cuda.synchronize()
+        oi, od = oracle.knn(X, Q, k)
+        np.testing.assert_array_equal(ids.cpu().numpy(), oi)
+        np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), od)
+
+
+def test_import_and_save_load_roundtrip(tiny, tiny_oracle, tmp_path):
+    Index = _index_cls()
+    X = tiny["X"]
+    imp = Index.from_parts(X, tiny_oracle["codebooks"], tiny_oracle["graph"], tiny_oracle["bridge_off"],
+                           tiny_oracle["bridge_ids"])
+    assert_search_equal(imp, tiny_oracle, X, tiny["Q"], 10, 256, 64)
+    path = str(tmp_path / "tiny.annidx")
+    imp.save(path)
+    back = Index.load(path)
+    p2 = back.export()
+    for key in ("codebooks", "graph", "bridge_off", "bridge_ids"):
+        np.testing.assert_array_equal(p2[key], tiny_oracle[key])
+    gi, gd = gpu_search(back, tiny["Q"], 10, 256, 64)
+    hi, hd = back.search(tiny["Q"], 10, 256, 64)
+    np.testing.assert_array_equal(gi, hi)
+    np.testing.assert_array_equal(gd, hd)
+
+
+def test_exhaustive_budget_returns_exact_knn():
+    """t=1, all references kept, T >= n: the search reaches every vector."""
+    w = synth.scaled(synth.WORKLOADS["tiny_10k_u8"], 1500, nq=30, K=8)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 6, 2, 8, 5, 9, 1, 0)
+    gi, gd = gpu_search(idx, Q, 20, 1500, 64)
+    oi, od = oracle.knn(X, Q, 20)
+    np.testing.assert_array_equal(gi, oi)
+    np.testing.assert_array_equal(gd.astype(np.float64), od)
+
+
+# ---------------------------------------------------------------- small variants, full build parity
+
+VARIANTS = [
+    # n, d, P, K, R, t, b, iters, hi
+    (700, 16, 1, 9, 5, 1, 0, 3, 256),
+    (900, 32, 2, 5, 8, 3, 2, 4, 6),      # tie-heavy values
+    (1000, 48, 3, 4, 7, 5, 0, 2, 256),
+    (1200, 64, 4, 6, 12, 100, 5, 3, 256),
+    (800, 128, 4, 3, 3, 2, 1, 1, 4),     # tie-heavy, tiny lists
+    (1300, 256, 2, 16, 16, 4, 3, 6, 256),
+]
+
+
+@pytest.mark.parametrize("n,d,P,K,R,t,b,iters,hi", VARIANTS)
+def test_variant_build_and_search_bit_exact(n, d, P, K, R, t, b, iters, hi):
+    rng = np.random.default_rng(n + d + P)
+    X = rng.integers(0, hi, size=(n, d)).astype(np.uint8)
+    X[7] = X[3]                               # duplicate vectors
+    Q = rng.integers(0, hi, size=(25, d)).astype(np.uint8)
+    Q[0] = X[5]                               # a query equal to a reference vector
+    idx = _index_cls().build(X, R, P, K, iters, 1234, t, b)
+    parts = idx.export()
+    cb = oracle.kmeans(X, P, K, iters, 1234)
+    np.testing.assert_array_equal(parts["codebooks"], cb)
+    g, _ = oracle.knn_graph_rows(X, np.arange(n), R)
+    np.testing.assert_array_equal(parts["graph"], g)
+    off, ids, _ = oracle.bridge_graph(X, cb, t, b)
+    np.testing.assert_array_equal(parts["bridge_off"], off)
+    np.testing.assert_array_equal(parts["bridge_ids"], ids)
+    for k, T, L in ((10, 200, 64), (3, 57, 1), (50, n, 16)):
+        assert_search_equal(idx, parts, X, Q, k, T, L)
+
+
+def test_graph_free_index():
+    """R = 0: only bridge lists are expanded."""
+    rng = np.random.default_rng(5)
+    X = rng.integers(0, 256, size=(600, 32)).astype(np.uint8)
+    Q = rng.integers(0, 256, size=(10, 32)).astype(np.uint8)
+    idx = _index_cls().build(X, 0, 2, 6, 3, 7, 1, 0)
+    parts = idx.export()
+    assert_search_equal(idx, parts, X, Q, 10, 600, 64)
+
+
+# ---------------------------------------------------------------- f32: tolerance against the FP64 oracle
+
+def test_f32_search_within_tolerance():
+    w = synth.scaled(synth.WORKLOADS["gist_like_1m_f32"], 4000, nq=50, K=12, d=96, P=3)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 8, 3, 12, 5, 3, 4, 3)
+    parts = idx.export()
+    gi, gd = gpu_search(idx, Q, 10, 300, 64)
+    oi, od = oracle.search(X, parts["codebooks"], parts["graph"], parts["bridge_off"], parts["bridge_ids"], Q,
+                           10, 300, 64)
+    # distances of the returned ids, recomputed in fp64, against the GPU's fp32 values
+    for i in range(len(Q)):
+        ex = ((X[gi[i]].astype(np.float64) - Q[i].astype(np.float64)) ** 2).sum(1)
+        np.testing.assert_allclose(gd[i], ex, rtol=1e-4)
+    gt, _ = oracle.knn(X, Q, 10)
+    from paper_1312_3062_amd import recall_at
+    assert abs(recall_at(gi, gt, 10) - recall_at(oi, gt, 10)) <= 0.002 + 1e-12
+    # bf16 gather with fp32 re-rank: returned distances are fp32-exact for the returned ids
+    bi, bd = gpu_search(idx, Q, 10, 300, 64, precision=1, rerank_k=20)
+    for i in range(len(Q)):
+        ex = ((X[bi[i]].astype(np.float64) - Q[i].astype(np.float64)) ** 2).sum(1)
+        np.testing.assert_allclose(bd[i], ex, rtol=1e-4)
+        assert (np.diff(bd[i]) >= 0).all()
