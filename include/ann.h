@@ -131,8 +131,9 @@ enum {
                                   empty ones and look-ahead included */
     ANN_STAT_HEAP_MAX = 5,     /* largest multi-sequence frontier */
     ANN_STAT_FLAGS = 6,        /* 0, or ANN_ERESOURCE if a structure overflowed */
-    ANN_STAT_RESERVED = 7,
-    ANN_NSTATS = 8
+    ANN_STAT_ROWS = 7,         /* vector rows gathered, look-ahead included */
+    ANN_STAT_LOOKAHEADS = 8,   /* batches of kNN rows loaded ahead */
+    ANN_NSTATS = 12            /* 9..11 reserved, written as 0 */
 };
 
 /* ------------------------------------------------------------------ */

@@ -14,8 +14,9 @@ ANN_U8, ANN_F32 = 0, 1
 ANN_OK, ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ESTATE, ANN_EUNSUPPORTED, ANN_EIO, ANN_ERESOURCE = (
     0, -1, -2, -3, -4, -5, -6, -7)
 PRECISION_EXACT, PRECISION_BF16_RERANK = 0, 1
-NSTATS = 8
-STAT_NAMES = ("evals", "ref_pops", "bridge_pops", "bridge_ids", "bridges_gen", "heap_max", "flags", "reserved")
+NSTATS = 12
+STAT_NAMES = ("evals", "ref_pops", "bridge_pops", "bridge_ids", "bridges_gen", "heap_max", "flags", "rows",
+              "lookaheads", "reserved9", "reserved10", "reserved11")
 
 
 class BuildParams(C.Structure):

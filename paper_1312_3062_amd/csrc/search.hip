@@ -2,19 +2,37 @@
 //
 // One wavefront (64 lanes, one workgroup) serves one query at a time:
 //   1. query tables: P x K squared subspace distances, each subspace sorted
-//      by (value, codeword)                                   (Sec. 4.2)
-//   2. multi-sequence extraction of bridge vectors in (distance, lid) order;
-//      the frontier is a binary heap in LDS driven by one lane.  Because the
-//      bridge order does not depend on the traversal, bridges are extracted
-//      ahead in batches and their CSR offsets are read by all lanes at once;
-//      empty bridges are dropped there (expanding one changes nothing).
-//                                                            (Sec. 3.3)
-//   3. best-first expansion: the smaller of the main-queue head and the
-//      next bridge is expanded; white neighbours are marked in an exact
-//      open-addressing hash in LDS, the first (T - t) of them in adjacency
-//      order are evaluated; each row is gathered by a group of lanes and
-//      reduced across the group; the results are merged into the bounded
-//      main queue and the result set, both sorted arrays in LDS. (Alg. 1)
+//      by (value, codeword)                                        (Sec. 4.2)
+//   2. multi-sequence extraction of bridge vectors in (distance, lid) order
+//      (Sec. 3.3).  The frontier is a binary heap driven by one lane; the
+//      bridge order does not depend on the traversal, so bridges are
+//      extracted ahead in batches and their CSR offsets read by all lanes at
+//      once.  Empty bridges are dropped there: expanding one changes nothing.
+//   3. best-first expansion (Alg. 1).  The adjacency row of a reference and
+//      its distance to the query are pure functions of ids, so the wave works
+//      ahead of the exact order: it loads the kNN rows of the S best queue
+//      entries together and gathers every neighbour that is neither visited
+//      nor already measured, all in one memory round trip.  Rows and
+//      distances stay in registers (lane s*R + j holds neighbour j of the
+//      s-th entry) and in an LDS distance cache.  The exact loop then pops in
+//      Alg. 1's order; a popped reference whose row is held is expanded with
+//      no memory access: its white neighbours are marked in the exact visited
+//      set, the first (T - t) of them in adjacency order are evaluated, and
+//      the results are merged into the bounded main queue and the result
+//      set.  Look-ahead never changes which vectors are evaluated, nor their
+//      order.
+//
+// Register layout: the main queue (L <= 64) is one key per lane, sorted,
+// with a head offset for pops; the result set is KPL keys per lane, sorted
+// (element e in lane e % 64, register e / 64).  A merge of m new keys costs
+// m scalar steps of ballots and one LDS scatter.
+//
+// The visited set and the distance cache are open-addressing tables of
+// 16-byte buckets (four 32-bit ids), probed a bucket at a time.
+//
+// The multi-sequence heap lives in LDS with a small capacity.  A query whose
+// frontier outgrows it is recorded and the same search is run again by a
+// second kernel that keeps the heap in global memory.
 #include "internal.hpp"
 #include "mseq.hpp"
 
@@ -24,6 +42,7 @@ namespace {
 enum { MODE_U8 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 
 constexpr int GEN_BATCH = 32;  // bridges extracted per look-ahead step
+constexpr int MAX_SPEC = 8;    // references whose rows are loaded ahead together
 
 struct SearchArgs {
     const uint8_t* X;     // rows that drive the search (u8, f32 or bf16)
@@ -46,18 +65,23 @@ struct SearchArgs {
     void* out_d;
     int32_t* stats;
     int32_t* trace;
-    int hash_bits;
+    uint32_t hash_buckets;  // visited set: buckets of 4 slots
+    uint32_t dc_buckets;    // distance cache: buckets of 4 slots
+    int spec;               // S, references loaded ahead (S * R <= 64)
     int heap_cap;
+    uint32_t* ovf_list;  // queries whose LDS heap overflowed
+    uint32_t* ovf_count;
+    uint8_t* gheap;      // re-run kernel: per-workgroup heap in global memory
+    int gheap_cap;
     // LDS layout (byte offsets)
-    int o_q, o_tab, o_sv, o_perm, o_hk, o_hr, o_rk, o_ro, o_rl, o_sk, o_hash, o_qa, o_qb, o_ra, o_rb, o_ek,
-        o_eid, o_sc;
+    int o_q, o_tab, o_sv, o_perm, o_hk, o_hr, o_rk, o_ro, o_rl, o_sk, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd, o_sc;
 };
 
 template <int MODE>
 struct Traits;
 template <>
 struct Traits<MODE_U8> {
-    static constexpr int LPR = 4;  // lanes per gathered row
+    static constexpr int LPR = 1;  // lanes per gathered row
     static constexpr bool FLOAT = false;
 };
 template <>
@@ -67,21 +91,49 @@ struct Traits<MODE_F32> {
 };
 template <>
 struct Traits<MODE_BF16> {
-    static constexpr int LPR = 16;
+    static constexpr int LPR = 8;
     static constexpr bool FLOAT = true;
 };
 
 // ------------------------------------------------------------------
-// squared distance of one gathered row, partial sum of this lane
+// squared distance of one gathered row; `part` of `lpr` lanes
 // ------------------------------------------------------------------
-template <int MODE>
-__device__ inline uint32_t row_partial(const uint8_t* row, const uint8_t* qv, int nc16, int part);
+template <int MODE, int NC16>
+__device__ inline uint32_t row_partial(const uint8_t* row, const uint8_t* qv, int nc16, int part, int lpr);
 
 template <>
-__device__ inline uint32_t row_partial<MODE_U8>(const uint8_t* row, const uint8_t* qv, int nc16, int part) {
+__device__ inline uint32_t row_partial<MODE_U8, 8>(const uint8_t* row, const uint8_t* qv, int, int, int) {
+    // d = 128: the whole 128-byte row in one lane, all loads in flight at once.
     // sum (q-x)^2 = sum q^2 + sum x^2 - 2 sum q*x, every term an exact integer
+    uint4 x[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = reinterpret_cast<const uint4*>(row)[c];
     uint32_t xx = 0, qq = 0, qx = 0;
-    for (int c = part; c < nc16; c += 4) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const uint4 q = *reinterpret_cast<const uint4*>(qv + c * 16);
+        xx = __builtin_amdgcn_udot4(x[c].x, x[c].x, xx, false);
+        xx = __builtin_amdgcn_udot4(x[c].y, x[c].y, xx, false);
+        xx = __builtin_amdgcn_udot4(x[c].z, x[c].z, xx, false);
+        xx = __builtin_amdgcn_udot4(x[c].w, x[c].w, xx, false);
+        qq = __builtin_amdgcn_udot4(q.x, q.x, qq, false);
+        qq = __builtin_amdgcn_udot4(q.y, q.y, qq, false);
+        qq = __builtin_amdgcn_udot4(q.z, q.z, qq, false);
+        qq = __builtin_amdgcn_udot4(q.w, q.w, qq, false);
+        qx = __builtin_amdgcn_udot4(q.x, x[c].x, qx, false);
+        qx = __builtin_amdgcn_udot4(q.y, x[c].y, qx, false);
+        qx = __builtin_amdgcn_udot4(q.z, x[c].z, qx, false);
+        qx = __builtin_amdgcn_udot4(q.w, x[c].w, qx, false);
+    }
+    return xx + qq - 2u * qx;
+}
+
+template <>
+__device__ inline uint32_t row_partial<MODE_U8, 0>(const uint8_t* row, const uint8_t* qv, int nc16, int part,
+                                                   int lpr) {
+    uint32_t xx = 0, qq = 0, qx = 0;
+#pragma unroll 4
+    for (int c = part; c < nc16; c += lpr) {
         const uint4 x = *reinterpret_cast<const uint4*>(row + c * 16);
         const uint4 q = *reinterpret_cast<const uint4*>(qv + c * 16);
         xx = __builtin_amdgcn_udot4(x.x, x.x, xx, false);
@@ -97,13 +149,15 @@ __device__ inline uint32_t row_partial<MODE_U8>(const uint8_t* row, const uint8_
         qx = __builtin_amdgcn_udot4(q.z, x.z, qx, false);
         qx = __builtin_amdgcn_udot4(q.w, x.w, qx, false);
     }
-    return xx + qq - 2u * qx;  // modulo 2^32; the 4-lane total is exact
+    return xx + qq - 2u * qx;  // modulo 2^32; the group total is exact
 }
 
 template <>
-__device__ inline uint32_t row_partial<MODE_F32>(const uint8_t* row, const uint8_t* qv, int nc16, int part) {
+__device__ inline uint32_t row_partial<MODE_F32, 0>(const uint8_t* row, const uint8_t* qv, int nc16, int part,
+                                                    int lpr) {
     float acc = 0.f;
-    for (int c = part; c < nc16; c += 16) {
+#pragma unroll 4
+    for (int c = part; c < nc16; c += lpr) {
         const float4 x = *reinterpret_cast<const float4*>(row + c * 16);
         const float4 q = *reinterpret_cast<const float4*>(qv + c * 16);
         float t0 = q.x - x.x, t1 = q.y - x.y, t2 = q.z - x.z, t3 = q.w - x.w;
@@ -116,10 +170,12 @@ __device__ inline uint32_t row_partial<MODE_F32>(const uint8_t* row, const uint8
 }
 
 template <>
-__device__ inline uint32_t row_partial<MODE_BF16>(const uint8_t* row, const uint8_t* qv, int nc16, int part) {
+__device__ inline uint32_t row_partial<MODE_BF16, 0>(const uint8_t* row, const uint8_t* qv, int nc16, int part,
+                                                     int lpr) {
     // row chunk c holds bf16 dims [8c, 8c+8); the query stays fp32
     float acc = 0.f;
-    for (int c = part; c < nc16; c += 16) {
+#pragma unroll 4
+    for (int c = part; c < nc16; c += lpr) {
         const uint4 x = *reinterpret_cast<const uint4*>(row + c * 16);
         const float4 qa = *reinterpret_cast<const float4*>(qv + c * 32);
         const float4 qb = *reinterpret_cast<const float4*>(qv + c * 32 + 16);
@@ -136,125 +192,237 @@ __device__ inline uint32_t row_partial<MODE_BF16>(const uint8_t* row, const uint
     return f_bits(acc);
 }
 
-// total over the LPR lanes of a row group (fixed butterfly order)
+// total over the lpr lanes of a row group (fixed butterfly order)
 template <int MODE>
-__device__ inline uint32_t group_sum(uint32_t v) {
+__device__ inline uint32_t group_sum(uint32_t v, int lpr) {
     if constexpr (!Traits<MODE>::FLOAT) {
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
+        for (int m = 1; m < lpr; m <<= 1) v += __shfl_xor(v, m);
         return v;
     } else {
         float f = bits_f(v);
-#pragma unroll
-        for (int m = 1; m < Traits<MODE>::LPR; m <<= 1) f += __shfl_xor(f, m);
+        for (int m = 1; m < lpr; m <<= 1) f += __shfl_xor(f, m);
         return f_bits(f);
     }
 }
 
-// ------------------------------------------------------------------
-// visited set: open addressing with linear probing, exact
-// ------------------------------------------------------------------
-__device__ inline bool hash_insert(uint32_t* H, int bits, uint32_t id) {
-    const uint32_t mask = (1u << bits) - 1u;
-    uint32_t s = (id * 0x9E3779B1u) >> (32 - bits);
-    for (;;) {
-        const uint32_t old = atomicCAS(&H[s], ID_EMPTY, id);
-        if (old == ID_EMPTY) return true;
-        if (old == id) return false;
-        s = (s + 1u) & mask;
+// Distance of the row `id` for every lane with `need`, returned in that lane.
+// One lane per row (u8); otherwise the rows are listed in LDS and groups of
+// LPR lanes gather them, RPP rows per pass.
+template <int MODE, int NC16>
+__device__ inline uint32_t gather_need(const SearchArgs& a, const uint8_t* qv, uint32_t id, bool need, uint32_t* gid,
+                                       uint32_t* gd, int lane) {
+    constexpr int LPR = Traits<MODE>::LPR;
+    if constexpr (LPR == 1) {
+        uint32_t d = 0;
+        if (need) d = row_partial<MODE, NC16>(a.X + int64_t(id) * a.row_bytes, qv, int(a.row_bytes / 16), 0, 1);
+        return d;
+    } else {
+        constexpr int RPP = WAVE / LPR;
+        const uint64_t nm = __ballot(need);
+        const int m = __popcll(nm);
+        const int pos = lanes_below(nm);
+        if (need) gid[pos] = id;
+        __syncthreads();
+        const int part = lane % LPR, grp = lane / LPR;
+        const int nc16 = int(a.row_bytes / 16);
+        for (int p0 = 0; p0 < m; p0 += RPP) {
+            const int row = p0 + grp;
+            uint32_t ps = 0;
+            if (row < m) ps = row_partial<MODE, 0>(a.X + int64_t(gid[row]) * a.row_bytes, qv, nc16, part, LPR);
+            const uint32_t dsum = group_sum<MODE>(ps, LPR);
+            if (part == 0 && row < m) gd[row] = dsum;
+        }
+        __syncthreads();
+        return need ? gd[pos] : 0u;
     }
 }
 
 // ------------------------------------------------------------------
-// Merge m new keys nk[0..m) (distinct, not present) into the sorted live
-// range src[h .. h+n), keep the `cap` smallest, write them to dst[0..).
-// Returns the new size.  Equivalent to offering the keys one by one to a
-// bounded set that evicts its largest key when full.
+// Exact sets of 32-bit ids: open addressing over 16-byte buckets of four
+// slots, linear probing bucket by bucket.  A bucket is read with one LDS
+// access; a slot is claimed with compare-and-swap.
 // ------------------------------------------------------------------
-__device__ int merge_keep(const uint64_t* src, int h, int n, uint64_t* dst, int cap, const uint64_t* nk, int m,
-                          int lane) {
-    const int total = min(cap, n + m);
-    for (int i = lane; i < n; i += WAVE) {
-        const uint64_t v = src[h + i];
-        int c = 0;
-        for (int j = 0; j < m; ++j) c += nk[j] < v;
-        const int pos = i + c;
-        if (pos < total) dst[pos] = v;
-    }
-    if (lane < m) {
-        const uint64_t v = nk[lane];
-        int c = 0;
-        for (int j = 0; j < m; ++j) c += nk[j] < v;
-        int lo = 0, hi = n;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (src[h + mid] < v)
-                lo = mid + 1;
-            else
-                hi = mid;
+__device__ inline uint32_t home_bucket(uint32_t id, uint32_t nbk) {
+    return uint32_t((uint64_t(id * 0x9E3779B1u) * nbk) >> 32);
+}
+
+// Slot of id, inserting it if absent.  fresh = it was absent.  Returns -1
+// (fresh = false) only if the table is full, which the callers' sizing rules
+// out; the probe count is bounded so that a wave can never spin here.
+__device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& fresh) {
+    uint32_t b = home_bucket(id, nbk);
+    for (uint32_t step = 0; step < 5 * nbk + 4; ++step) {
+        const uint4 v = reinterpret_cast<const uint4*>(T)[b];
+        int e = -1;
+        if (v.x == id) e = 0;
+        else if (v.y == id) e = 1;
+        else if (v.z == id) e = 2;
+        else if (v.w == id) e = 3;
+        if (e >= 0) {
+            fresh = false;
+            return int(b * 4 + e);
         }
-        const int pos = c + lo;
-        if (pos < total) dst[pos] = v;
+        const int f = v.x == ID_EMPTY ? 0 : v.y == ID_EMPTY ? 1 : v.z == ID_EMPTY ? 2 : v.w == ID_EMPTY ? 3 : -1;
+        if (f < 0) {
+            b = (b + 1 == nbk) ? 0 : b + 1;
+            continue;
+        }
+        const uint32_t old = atomicCAS(&T[b * 4 + f], ID_EMPTY, id);
+        if (old == ID_EMPTY || old == id) {
+            fresh = old == ID_EMPTY;
+            return int(b * 4 + f);
+        }
+        // another lane took the slot for a different id: read the bucket again
+    }
+    fresh = false;
+    return -1;
+}
+
+// Slot of id, or -1.
+__device__ inline int set_find(const uint32_t* T, uint32_t nbk, uint32_t id) {
+    uint32_t b = home_bucket(id, nbk);
+    for (uint32_t step = 0; step < nbk; ++step) {
+        const uint4 v = reinterpret_cast<const uint4*>(T)[b];
+        if (v.x == id) return int(b * 4);
+        if (v.y == id) return int(b * 4 + 1);
+        if (v.z == id) return int(b * 4 + 2);
+        if (v.w == id) return int(b * 4 + 3);
+        if (v.x == ID_EMPTY || v.y == ID_EMPTY || v.z == ID_EMPTY || v.w == ID_EMPTY) return -1;
+        b = (b + 1 == nbk) ? 0 : b + 1;
+    }
+    return -1;
+}
+
+// ------------------------------------------------------------------
+// Sorted key arrays held in registers
+// ------------------------------------------------------------------
+__device__ inline uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v)), l));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(v >> 32)), l));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+template <int KPL>
+__device__ inline uint64_t reg_get(const uint64_t (&v)[KPL], int e) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int u = 0; u < KPL; ++u)
+        if (e / WAVE == u) r = readlane64(v[u], e % WAVE);
+    return r;
+}
+
+// Merge the keys of the lanes with `isnew` (distinct, none present) into the
+// sorted array v[h .. h+n), keep the `cap` smallest, leave them in v[0..).
+// Same result as offering the keys one by one to a bounded set that evicts
+// its largest key when full.
+template <int KPL>
+__device__ inline void reg_merge(uint64_t (&v)[KPL], int& h, int& n, int cap, uint64_t x, bool isnew,
+                                 uint64_t* scratch, int lane) {
+    uint64_t nm = __ballot(isnew);
+    const int m = __popcll(nm);
+    int c_old[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) c_old[u] = 0;
+    int rank_new = 0, c_new = 0;
+    while (nm) {
+        const int j = __builtin_ctzll(nm);
+        nm &= nm - 1;
+        const uint64_t xj = readlane64(x, j);
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) {
+            const int e = lane + u * WAVE;
+            const bool live = e >= h && e < h + n;
+            c_old[u] += (live && xj < v[u]) ? 1 : 0;
+            cnt += __popcll(__ballot(live && v[u] < xj));
+        }
+        rank_new += xj < x ? 1 : 0;
+        if (lane == j) c_new = cnt;
+    }
+    const int total = min(cap, n + m);
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+        const int e = lane + u * WAVE;
+        if (e >= h && e < h + n) {
+            const int pos = e - h + c_old[u];
+            if (pos < total) scratch[pos] = v[u];
+        }
+    }
+    if (isnew) {
+        const int pos = rank_new + c_new;
+        if (pos < total) scratch[pos] = x;
     }
     __syncthreads();
-    return total;
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+        const int e = lane + u * WAVE;
+        v[u] = e < total ? scratch[e] : KEY_EMPTY;
+    }
+    __syncthreads();
+    h = 0;
+    n = total;
 }
 
-// true if any of the m new keys would enter a set of capacity cap
-__device__ inline bool any_admitted(const uint64_t* src, int h, int n, int cap, const uint64_t* nk, int m, int lane) {
-    if (m == 0 || cap == 0) return false;
-    if (n < cap) return true;
-    const uint64_t worst = src[h + n - 1];
-    return __ballot(lane < m && nk[lane] < worst) != 0;
-}
-
-template <int MODE>
+template <int MODE, int NC16, int KPL, bool RERUN>
 __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr bool FLOAT = Traits<MODE>::FLOAT;
-    constexpr int LPR = Traits<MODE>::LPR;
-    constexpr int RPP = WAVE / LPR;  // rows per gather pass
 
     uint8_t* qv = lds + a.o_q;
     uint32_t* tab = reinterpret_cast<uint32_t*>(lds + a.o_tab);
     uint32_t* sv = reinterpret_cast<uint32_t*>(lds + a.o_sv);
     uint8_t* perm = lds + a.o_perm;
-    uint64_t* hk = reinterpret_cast<uint64_t*>(lds + a.o_hk);
-    uint32_t* hr = reinterpret_cast<uint32_t*>(lds + a.o_hr);
     uint64_t* ring_key = reinterpret_cast<uint64_t*>(lds + a.o_rk);
     uint32_t* ring_off = reinterpret_cast<uint32_t*>(lds + a.o_ro);
     uint32_t* ring_len = reinterpret_cast<uint32_t*>(lds + a.o_rl);
     uint64_t* stage = reinterpret_cast<uint64_t*>(lds + a.o_sk);
     uint32_t* H = reinterpret_cast<uint32_t*>(lds + a.o_hash);
-    uint64_t* QA = reinterpret_cast<uint64_t*>(lds + a.o_qa);
-    uint64_t* QB = reinterpret_cast<uint64_t*>(lds + a.o_qb);
-    uint64_t* RA = reinterpret_cast<uint64_t*>(lds + a.o_ra);
-    uint64_t* RB = reinterpret_cast<uint64_t*>(lds + a.o_rb);
-    uint64_t* ek = reinterpret_cast<uint64_t*>(lds + a.o_ek);
-    uint32_t* eid = reinterpret_cast<uint32_t*>(lds + a.o_eid);
+    uint32_t* DK = reinterpret_cast<uint32_t*>(lds + a.o_dck);
+    uint32_t* DV = reinterpret_cast<uint32_t*>(lds + a.o_dcv);
+    uint64_t* scratch = reinterpret_cast<uint64_t*>(lds + a.o_scr);
+    uint32_t* gid = reinterpret_cast<uint32_t*>(lds + a.o_gid);
+    uint32_t* gd = reinterpret_cast<uint32_t*>(lds + a.o_gd);
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
 
-    const int lane = lane_id();
-    const int part = lane % LPR;
-    const int grp = lane / LPR;
-    const int64_t n = a.n;
-    const int P = a.P, K = a.K;
-    const int HS = 1 << a.hash_bits;
-    const int qbytes = FLOAT ? a.d * 4 : a.d;
-    const int nc16 = int(a.row_bytes / 16);
+    uint64_t* hk;
+    uint32_t* hr;
+    int heap_cap;
+    if constexpr (RERUN) {
+        hk = reinterpret_cast<uint64_t*>(a.gheap + int64_t(blockIdx.x) * a.gheap_cap * 12);
+        hr = reinterpret_cast<uint32_t*>(hk + a.gheap_cap);
+        heap_cap = a.gheap_cap;
+    } else {
+        hk = reinterpret_cast<uint64_t*>(lds + a.o_hk);
+        hr = reinterpret_cast<uint32_t*>(lds + a.o_hr);
+        heap_cap = a.heap_cap;
+    }
 
-    for (int64_t qi = blockIdx.x; qi < a.nq; qi += gridDim.x) {
+    const int lane = lane_id();
+    const int64_t n = a.n;
+    const int P = a.P, K = a.K, R = a.R;
+    const int HW = int(a.hash_buckets) * 4;
+    const int DW = int(a.dc_buckets) * 4;
+    const int dc_limit = DW / 2 - WAVE;  // keeps the cache at most about half full
+    const int qbytes = FLOAT ? a.d * 4 : a.d;
+    const int S = a.spec;
+    const int row_lane_slot = R > 0 ? lane / R : 0;  // which look-ahead entry this lane serves
+    const int row_lane_j = R > 0 ? lane % R : 0;
+
+    const int64_t nwork = RERUN ? int64_t(*a.ovf_count) : a.nq;
+    for (int64_t wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+        const int64_t qi = RERUN ? int64_t(a.ovf_list[wi]) : wi;
         // per-query values are clamped to the launch maxima that sized the buffers
         const int k = a.ks ? min(max(a.ks[qi], 1), a.kmax) : a.kmax;
         const int T = a.Ts ? min(max(a.Ts[qi], 0), a.Tmax) : a.Tmax;
         const int rcap = (MODE == MODE_BF16) ? max(k, a.rerank_k) : k;
 
-        // ---- load the query, clear the visited set
+        // ---- load the query, clear the visited set and the distance cache
         {
             const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(a.Q) + qi * qbytes);
             uint32_t* dst = reinterpret_cast<uint32_t*>(qv);
             for (int i = lane; i < qbytes / 4; i += WAVE) dst[i] = src[i];
-            for (int i = lane; i < HS; i += WAVE) H[i] = ID_EMPTY;
+            for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
+            for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
         }
         __syncthreads();
 
@@ -264,7 +432,6 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             int hn = 0;
             heap_push(hk, hr, hn, tuple_key<FLOAT>(0u, sv, perm, P, K, n), 0u);
             sc[0] = hn;
-            sc[1] = 0;  // overflow flag
         }
         __syncthreads();
 
@@ -272,182 +439,266 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         int heap_max = heap_n;
         int flags = 0;
         int ring_h = 0, ring_n = 0;
-        int qh = 0, qn = 0, rn = 0;
-        uint64_t* Qc = QA;
-        uint64_t* Qn = QB;
-        uint64_t* Rc = RA;
-        uint64_t* Rn = RB;
+        uint64_t bkey = KEY_EMPTY;  // next non-empty bridge (ring head)
+        uint64_t Qv[1] = {KEY_EMPTY};
+        int qh = 0, qn = 0;
+        uint64_t Rv[KPL];
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) Rv[u] = KEY_EMPTY;
+        int rh = 0, rn = 0;
+        // look-ahead rows: lane l holds neighbour (l % R) of entry (l / R)
+        uint32_t acn = ID_EMPTY;  // lane s < S: node id of entry s
+        uint32_t ac_id = ID_EMPTY, ac_d = 0;
         int t = 0;
-        int st_rpop = 0, st_bpop = 0, st_bids = 0, st_gen = 0;
+        int dc_fill = 0;
+        int st_rpop = 0, st_bpop = 0, st_bids = 0, st_gen = 0, st_rows = 0, st_spec = 0;
+        int r = 0;
+
+        // the lanes with `ev` hold evaluated keys (rank r in adjacency order):
+        // record them and offer them to the result set and the main queue
+        auto offer = [&](uint64_t key, bool ev) {
+            if (a.trace && ev) a.trace[qi * a.Tmax + t + r] = int32_t(key_id(key));
+            const uint64_t rworst = rn < rcap ? KEY_EMPTY : reg_get<KPL>(Rv, rn - 1);
+            const bool ra = ev && key < rworst;
+            if (__ballot(ra)) reg_merge<KPL>(Rv, rh, rn, rcap, key, ra, scratch, lane);
+            const uint64_t qworst = qn < a.L ? KEY_EMPTY : readlane64(Qv[0], qh + qn - 1);
+            const bool qa = ev && key < qworst;
+            if (__ballot(qa)) reg_merge<1>(Qv, qh, qn, a.L, key, qa, scratch, lane);
+        };
 
         while (t < T) {
             // ---- look-ahead extraction of the next non-empty bridges
-            while (ring_h == ring_n && heap_n > 0 && flags == 0) {
-                if (lane == 0) {
-                    int hn = heap_n, g = 0, of = 0;
-                    for (; g < GEN_BATCH && hn > 0; ++g) {
-                        uint64_t key;
-                        uint32_t rk;
-                        heap_pop(hk, hr, hn, key, rk);
-                        stage[g] = key;
-                        // unique-parent rule: raise one rank at or after the last non-zero one
-                        int last = 0;
-                        for (int p = 0; p < P; ++p)
-                            if ((rk >> (8 * p)) & 0xFF) last = p;
-                        for (int b = last; b < P; ++b) {
-                            const int r = (rk >> (8 * b)) & 0xFF;
-                            if (r + 1 >= K) continue;
-                            if (hn >= a.heap_cap) {
-                                of = 1;
+            if (ring_h == ring_n) {
+                while (ring_h == ring_n && heap_n > 0 && flags == 0) {
+                    if (lane == 0) {
+                        int hn = heap_n, g = 0, of = 0;
+                        for (; g < GEN_BATCH && hn > 0; ++g) {
+                            uint64_t key;
+                            uint32_t rk;
+                            heap_pop(hk, hr, hn, key, rk);
+                            stage[g] = key;
+                            // unique-parent rule: raise one rank at or after the last non-zero one
+                            int last = 0;
+                            for (int p = 0; p < P; ++p)
+                                if ((rk >> (8 * p)) & 0xFF) last = p;
+                            for (int b = last; b < P; ++b) {
+                                const int r = (rk >> (8 * b)) & 0xFF;
+                                if (r + 1 >= K) continue;
+                                if (hn >= heap_cap) {
+                                    of = 1;
+                                    break;
+                                }
+                                const uint32_t crk = rk + (1u << (8 * b));
+                                heap_push(hk, hr, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, n), crk);
+                            }
+                            if (of) {
+                                ++g;
                                 break;
                             }
-                            const uint32_t crk = rk + (1u << (8 * b));
-                            heap_push(hk, hr, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, n), crk);
                         }
-                        if (of) {
-                            ++g;
-                            break;
-                        }
+                        sc[0] = hn;
+                        sc[1] = of;
+                        sc[2] = g;
                     }
-                    sc[0] = hn;
-                    sc[1] = of;
-                    sc[2] = g;
+                    __syncthreads();
+                    heap_n = sc[0];
+                    heap_max = max(heap_max, heap_n);
+                    const int g = sc[2];
+                    if (sc[1]) flags = ANN_ERESOURCE;
+                    st_gen += g;
+                    bool ne = false;
+                    uint64_t key = 0;
+                    uint32_t o0 = 0, o1 = 0;
+                    if (lane < g) {
+                        key = stage[lane];
+                        const uint32_t lid = key_id(key) - uint32_t(n);
+                        o0 = a.boff[lid];
+                        o1 = a.boff[lid + 1];
+                        ne = o1 > o0;
+                    }
+                    const uint64_t mask = __ballot(ne);
+                    if (ne) {
+                        const int pos = lanes_below(mask);
+                        ring_key[pos] = key;
+                        ring_off[pos] = o0;
+                        ring_len[pos] = o1 - o0;
+                    }
+                    ring_h = 0;
+                    ring_n = __popcll(mask);
+                    __syncthreads();
                 }
-                __syncthreads();
-                heap_n = sc[0];
-                heap_max = max(heap_max, heap_n);
-                const int g = sc[2];
-                if (sc[1]) flags = ANN_ERESOURCE;
-                st_gen += g;
-                bool ne = false;
-                uint64_t key = 0;
-                uint32_t o0 = 0, o1 = 0;
-                if (lane < g) {
-                    key = stage[lane];
-                    const uint32_t lid = key_id(key) - uint32_t(n);
-                    o0 = a.boff[lid];
-                    o1 = a.boff[lid + 1];
-                    ne = o1 > o0;
-                }
-                const uint64_t mask = __ballot(ne);
-                if (ne) {
-                    const int pos = lanes_below(mask);
-                    ring_key[pos] = key;
-                    ring_off[pos] = o0;
-                    ring_len[pos] = o1 - o0;
-                }
-                ring_h = 0;
-                ring_n = __popcll(mask);
-                __syncthreads();
+                bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
             }
             if (flags) break;
 
-            // ---- pop the best of the queue head and the next bridge
-            const uint64_t bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
-            const uint64_t qkey = qn > 0 ? Qc[qh] : KEY_EMPTY;
-            const uint32_t* src;
-            int64_t base;
-            int len;
-            if (ring_h < ring_n && bkey < qkey) {
-                src = a.bids;
-                base = ring_off[ring_h];
-                len = int(ring_len[ring_h]);
-                ++ring_h;
-                ++st_bpop;
-                st_bids += len;
-            } else if (qn > 0) {
-                src = a.G;
-                base = int64_t(key_id(qkey)) * a.R;
-                len = a.R;
+            // ---- which vertex Alg. 1 pops next: the queue head or the next bridge
+            const uint64_t qkey = qn > 0 ? readlane64(Qv[0], qh) : KEY_EMPTY;
+            const bool use_bridge = ring_h < ring_n && bkey < qkey;
+            if (!use_bridge && qn == 0) break;  // queue empty and every bridge consumed
+
+            bool ev = false, full = false;
+            uint32_t id = ID_EMPTY, dist = 0;
+            int take = 0;
+            if (!use_bridge) {
+                // ---- a reference: find its row among the rows loaded ahead
+                const uint32_t node = key_id(qkey);
+                uint64_t hit = __ballot(lane < S && acn == node);
+                if (!hit) {
+                    // work ahead: rows of the S best queue entries, distances of
+                    // their unvisited neighbours not yet in the cache
+                    ++st_spec;
+                    if (dc_fill > dc_limit) {
+                        for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
+                        dc_fill = 0;
+                        __syncthreads();
+                    }
+                    const int ns = min(S, qn);
+                    acn = ID_EMPTY;
+                    for (int s = 0; s < ns; ++s) {
+                        const uint32_t nd = key_id(readlane64(Qv[0], qh + s));
+                        if (lane == s) acn = nd;
+                    }
+                    ac_id = ID_EMPTY;
+                    const uint32_t nd_l = uint32_t(__shfl(int(acn), row_lane_slot));
+                    if (R > 0 && lane < ns * R) ac_id = a.G[int64_t(nd_l) * R + row_lane_j];
+                    bool need = false, known = false;
+                    int slot = 0;
+                    if (ac_id != ID_EMPTY && set_find(H, a.hash_buckets, ac_id) < 0) {
+                        known = true;
+                        slot = set_insert(DK, a.dc_buckets, ac_id, need);
+                        if (slot < 0) {
+                            full = true;
+                            slot = 0;
+                            known = false;
+                        }
+                    }
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, ac_id, need, gid, gd, lane);
+                    if (need) DV[slot] = gdist;
+                    const int m = __popcll(__ballot(need));
+                    dc_fill += m;
+                    st_rows += m;
+                    __syncthreads();
+                    ac_d = known ? (need ? gdist : DV[slot]) : 0u;
+                    hit = 1;  // entry 0 is the queue head
+                }
+                const int s = __builtin_ctzll(hit);
                 ++qh;
                 --qn;
                 ++st_rpop;
+                // ---- expand: the row sits in lanes [s*R, s*R + R)
+                const bool inrow = R > 0 && row_lane_slot == s && lane < (s + 1) * R;
+                bool white = false;
+                if (inrow && ac_id != ID_EMPTY && set_insert(H, a.hash_buckets, ac_id, white) < 0) full = true;
+                const uint64_t wm = __ballot(white);
+                take = min(int(__popcll(wm)), T - t);
+                r = lanes_below(wm);
+                ev = white && r < take;
+                id = ac_id;
+                dist = ac_d;
             } else {
-                break;  // queue empty and every bridge consumed
+                // ---- a bridge: its list of references (Sec. 4.1 bridge graph)
+                const int64_t base = ring_off[ring_h];
+                const int len = int(ring_len[ring_h]);
+                ++ring_h;
+                bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
+                ++st_bpop;
+                st_bids += len;
+                // lists longer than a wave are walked in chunks; every chunk but
+                // the one that ends the list or the budget is merged here, that
+                // one below
+                for (int c0 = 0;; c0 += WAVE) {
+                    const int j = c0 + lane;
+                    id = j < len ? a.bids[base + j] : ID_EMPTY;
+                    bool white = false;
+                    if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
+                    const uint64_t wm = __ballot(white);
+                    take = min(int(__popcll(wm)), T - t);
+                    r = lanes_below(wm);
+                    ev = white && r < take;
+                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
+                    const bool miss = ev && slot < 0;
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
+                    st_rows += __popcll(__ballot(miss));
+                    dist = slot >= 0 ? DV[slot] : gdist;
+                    if (c0 + WAVE >= len || t + take >= T) break;
+                    offer(make_key(dist, id), ev);
+                    t += take;
+                }
             }
 
-            // ---- expand: 64 adjacency entries at a time
-            for (int c0 = 0; c0 < len && t < T; c0 += WAVE) {
-                const int j = c0 + lane;
-                const uint32_t id = j < len ? src[base + j] : ID_EMPTY;
-                const bool white = id != ID_EMPTY && hash_insert(H, a.hash_bits, id);
-                const uint64_t wm = __ballot(white);
-                const int take = min(int(__popcll(wm)), T - t);
-                const int r = lanes_below(wm);
-                if (white && r < take) eid[r] = id;
-                __syncthreads();
-
-                // gather and distance, RPP rows per pass
-                for (int p0 = 0; p0 < take; p0 += RPP) {
-                    const int row = p0 + grp;
-                    uint32_t part_sum = 0;
-                    uint32_t rid = 0;
-                    if (row < take) {
-                        rid = eid[row];
-                        part_sum = row_partial<MODE>(a.X + int64_t(rid) * a.row_bytes, qv, nc16, part);
-                    }
-                    const uint32_t dsum = group_sum<MODE>(part_sum);
-                    if (part == 0 && row < take) ek[row] = make_key(dsum, rid);
-                }
-                __syncthreads();
-                if (a.trace && lane < take) a.trace[qi * a.Tmax + t + lane] = int32_t(eid[lane]);
-
-                if (any_admitted(Rc, 0, rn, rcap, ek, take, lane)) {
-                    rn = merge_keep(Rc, 0, rn, Rn, rcap, ek, take, lane);
-                    uint64_t* tmp = Rc;
-                    Rc = Rn;
-                    Rn = tmp;
-                }
-                if (any_admitted(Qc, qh, qn, a.L, ek, take, lane)) {
-                    qn = merge_keep(Qc, qh, qn, Qn, a.L, ek, take, lane);
-                    qh = 0;
-                    uint64_t* tmp = Qc;
-                    Qc = Qn;
-                    Qn = tmp;
-                }
+            if (__ballot(full)) {  // a table outgrew its sizing: give up on this query
+                flags = ANN_ERESOURCE;
+                break;
+            }
+            // ---- evaluated vectors enter the result set and the main queue
+            if (take > 0) {
+                offer(make_key(dist, id), ev);
                 t += take;
             }
         }
 
+        if (!RERUN && flags) {
+            // the LDS heap overflowed: the re-run kernel redoes this query
+            if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1u)] = uint32_t(qi);
+            __syncthreads();
+            continue;
+        }
+
         // ---- bf16 mode: re-rank the kept candidates with fp32 rows
         if constexpr (MODE == MODE_BF16) {
+#pragma unroll
+            for (int u = 0; u < KPL; ++u) {
+                const int e = lane + u * WAVE;
+                if (e < rn) scratch[e] = Rv[u];
+            }
+            __syncthreads();
+            constexpr int LPR = 16, RPP = WAVE / LPR;
+            const int part = lane % LPR, grp = lane / LPR;
             const int nc16f = int(a.row_bytes_f32 / 16);
+            uint64_t* rr = reinterpret_cast<uint64_t*>(gid);  // rn <= rcap keys (sized by the host)
             for (int p0 = 0; p0 < rn; p0 += RPP) {
                 const int row = p0 + grp;
                 uint32_t part_sum = 0, rid = 0;
                 if (row < rn) {
-                    rid = key_id(Rc[row]);
-                    part_sum = row_partial<MODE_F32>(a.Xf32 + int64_t(rid) * a.row_bytes_f32, qv, nc16f, part);
+                    rid = key_id(scratch[row]);
+                    part_sum = row_partial<MODE_F32, 0>(a.Xf32 + int64_t(rid) * a.row_bytes_f32, qv, nc16f, part, LPR);
                 }
-                const uint32_t dsum = group_sum<MODE_F32>(part_sum);
-                if (part == 0 && row < rn) Rn[row] = make_key(dsum, rid);
+                const uint32_t dsum = group_sum<MODE_F32>(part_sum, LPR);
+                if (part == 0 && row < rn) rr[row] = make_key(dsum, rid);
             }
             __syncthreads();
             for (int i = lane; i < rn; i += WAVE) {
-                const uint64_t v = Rn[i];
-                int r = 0;
-                for (int jj = 0; jj < rn; ++jj) r += Rn[jj] < v;
-                Rc[r] = v;
+                const uint64_t v = rr[i];
+                int rk = 0;
+                for (int jj = 0; jj < rn; ++jj) rk += rr[jj] < v;
+                scratch[rk] = v;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < KPL; ++u) {
+                const int e = lane + u * WAVE;
+                Rv[u] = e < rn ? scratch[e] : KEY_EMPTY;
             }
             __syncthreads();
         }
 
         // ---- results, ascending by (distance, id), padded
-        for (int i = lane; i < a.kmax; i += WAVE) {
-            const int64_t o = qi * a.kmax + i;
-            if (flags == 0 && i < k && i < rn) {
-                const uint64_t v = Rc[i];
-                a.out_ids[o] = int32_t(key_id(v));
-                static_cast<uint32_t*>(a.out_d)[o] = key_dist(v);
-            } else {
-                a.out_ids[o] = -1;
-                static_cast<uint32_t*>(a.out_d)[o] = FLOAT ? 0x7F800000u : 0x7FFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) {
+            const int i = lane + u * WAVE;
+            if (i < a.kmax) {
+                const int64_t o = qi * a.kmax + i;
+                if (flags == 0 && i < k && i < rn) {
+                    a.out_ids[o] = int32_t(key_id(Rv[u]));
+                    static_cast<uint32_t*>(a.out_d)[o] = key_dist(Rv[u]);
+                } else {
+                    a.out_ids[o] = -1;
+                    static_cast<uint32_t*>(a.out_d)[o] = FLOAT ? 0x7F800000u : 0x7FFFFFFFu;
+                }
             }
         }
         if (a.trace)
-            for (int i = t + lane; i < T; i += WAVE) a.trace[qi * a.Tmax + i] = -1;
-        if (a.trace)
-            for (int i = T + lane; i < a.Tmax; i += WAVE) a.trace[qi * a.Tmax + i] = -1;
+            for (int i = t + lane; i < a.Tmax; i += WAVE) a.trace[qi * a.Tmax + i] = -1;
         if (a.stats && lane == 0) {
             int32_t* s = a.stats + qi * ANN_NSTATS;
             s[ANN_STAT_EVALS] = t;
@@ -457,10 +708,19 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             s[ANN_STAT_BRIDGES_GEN] = st_gen;
             s[ANN_STAT_HEAP_MAX] = heap_max;
             s[ANN_STAT_FLAGS] = flags;
-            s[ANN_STAT_RESERVED] = 0;
+            s[ANN_STAT_ROWS] = st_rows;
+            s[ANN_STAT_LOOKAHEADS] = st_spec;
+            s[ANN_STAT_LOOKAHEADS + 1] = 0;
+            s[ANN_STAT_LOOKAHEADS + 2] = 0;
+            s[ANN_STAT_LOOKAHEADS + 3] = 0;
         }
+        (void)rh;
         __syncthreads();
     }
+}
+
+__global__ void k_zero_u32(uint32_t* p) {
+    if (threadIdx.x == 0) *p = 0;
 }
 
 // standalone tables kernel (query preprocessing only)
@@ -490,11 +750,59 @@ __global__ void __launch_bounds__(WAVE) k_tables(const void* Q, int64_t nq, int 
 
 int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
+// LDS layout of one query's state; the heap is left out for the re-run kernel
+int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap) {
+    int off = 0;
+    auto take = [&](int bytes, int al) {
+        off = align_up(off, al);
+        int o = off;
+        off += bytes;
+        return o;
+    };
+    a.o_q = take(align_up(qbytes, 16), 16);
+    a.o_tab = take(PK * 4, 8);
+    a.o_sv = take(PK * 4, 8);
+    a.o_perm = take(PK, 8);
+    a.o_hk = with_heap ? take(a.heap_cap * 8, 8) : 0;
+    a.o_hr = with_heap ? take(a.heap_cap * 4, 8) : 0;
+    a.o_rk = take(WAVE * 8, 8);
+    a.o_ro = take(WAVE * 4, 8);
+    a.o_rl = take(WAVE * 4, 8);
+    a.o_sk = take(WAVE * 8, 8);
+    a.o_hash = take(int(a.hash_buckets) * 16, 16);
+    a.o_dck = take(int(a.dc_buckets) * 16, 16);
+    a.o_dcv = take(int(a.dc_buckets) * 16, 16);
+    a.o_scr = take(std::max(std::max(a.L, rcap), WAVE) * 8, 8);
+    a.o_gid = take(std::max(WAVE, rcap * 2) * 4, 8);  // also holds the re-rank keys
+    a.o_gd = take(WAVE * 4, 8);
+    a.o_sc = take(16 * 4, 8);
+    return align_up(off, 16);
+}
+
+template <int MODE, int NC16, int KPL>
+void launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, int64_t grid, int grid2,
+                 hipStream_t st) {
+    hipLaunchKernelGGL((k_search<MODE, NC16, KPL, false>), dim3(unsigned(grid)), dim3(WAVE), lds1, st, a1);
+    hipLaunchKernelGGL((k_search<MODE, NC16, KPL, true>), dim3(unsigned(grid2)), dim3(WAVE), lds2, st, a2);
+}
+
+template <int MODE, int NC16>
+void launch_kpl(int rcap, const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, int64_t grid, int grid2,
+                hipStream_t st) {
+    if (rcap <= 64)
+        launch_mode<MODE, NC16, 1>(a1, a2, lds1, lds2, grid, grid2, st);
+    else if (rcap <= 128)
+        launch_mode<MODE, NC16, 2>(a1, a2, lds1, lds2, grid, grid2, st);
+    else
+        launch_mode<MODE, NC16, 16>(a1, a2, lds1, lds2, grid, grid2, st);
+}
+
 }  // namespace
 
 int launch_search(const SearchLaunch& s) {
     const ann_index* idx = s.idx;
     if (s.nq == 0) return ANN_OK;
+    ANN_REQUIRE(idx->R <= WAVE, "search: graph out-degree above 64 is not supported");
     SearchArgs a{};
     const bool is_f32 = idx->dtype == ANN_F32;
     const bool bf16 = is_f32 && s.precision == ANN_PRECISION_BF16_RERANK;
@@ -529,60 +837,61 @@ int launch_search(const SearchLaunch& s) {
     a.stats = s.d_stats;
     a.trace = s.d_trace;
 
-    // visited set: >= 1.5 x (budget + one adjacency chunk) slots, a power of two
-    int bits = 6;
-    while ((1 << bits) < (3 * (s.Tmax + WAVE)) / 2) ++bits;
-    a.hash_bits = bits;
-    // multi-sequence frontier: one pop adds at most P - 1 entries; it never
-    // holds more than the K^P tuples
-    a.heap_cap = int(std::min<int64_t>(idx->nb, std::max(256, s.Tmax + 64 * idx->P)));
+    // visited set: at most T + 64 ids (the last adjacency chunk may mark more
+    // than it evaluates); buckets for a final load of about 0.75
+    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 4 / 3 / 4 + 1));
+    a.dc_buckets = 128;  // distance cache: 512 slots, cleared when half full
+    a.spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
+    // LDS frontier of the multi-sequence; larger ones go to the re-run kernel
+    a.heap_cap = int(std::min<int64_t>(idx->nb, 320));
 
     const int qbytes = is_f32 ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
     const int rcap = bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
-    int off = 0;
-    auto take = [&](int bytes, int al) {
-        off = align_up(off, al);
-        int o = off;
-        off += bytes;
-        return o;
-    };
-    a.o_q = take(align_up(qbytes, 16), 16);
-    a.o_tab = take(PK * 4, 8);
-    a.o_sv = take(PK * 4, 8);
-    a.o_perm = take(PK, 8);
-    a.o_hk = take(a.heap_cap * 8, 8);
-    a.o_hr = take(a.heap_cap * 4, 8);
-    a.o_rk = take(WAVE * 8, 8);
-    a.o_ro = take(WAVE * 4, 8);
-    a.o_rl = take(WAVE * 4, 8);
-    a.o_sk = take(WAVE * 8, 8);
-    a.o_hash = take((1 << bits) * 4, 8);
-    a.o_qa = take(s.L * 8, 8);
-    a.o_qb = take(s.L * 8, 8);
-    a.o_ra = take(rcap * 8, 8);
-    a.o_rb = take(rcap * 8, 8);
-    a.o_ek = take(WAVE * 8, 8);
-    a.o_eid = take(WAVE * 4, 8);
-    a.o_sc = take(16 * 4, 8);
-    const int lds_bytes = align_up(off, 16);
+    ANN_REQUIRE(rcap <= 1024, "search: k (or rerank_k) above 1024");
+    SearchArgs a2 = a;
+    const int lds1 = layout(a, qbytes, PK, rcap, true);
+    const int lds2 = layout(a2, qbytes, PK, rcap, false);
 
     int dev = 0, max_lds = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (lds_bytes > max_lds)
-        return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(lds_bytes) +
+    if (lds1 > max_lds)
+        return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(lds1) +
                                                " bytes of LDS per query, more than the device's " +
                                                std::to_string(max_lds) + " (lower budget or k)");
+
+    // re-run workspace: overflow list, its counter, one global heap per workgroup
+    const int grid2 = 64;
+    const int64_t gcap = std::min<int64_t>(idx->nb, std::max<int64_t>(4096, 8 * int64_t(s.Tmax) + 1024));
+    const size_t ws = size_t(s.nq) * 4 + 256 + 16 + size_t(grid2) * size_t(gcap) * 12;
+    uint8_t* w = nullptr;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), ws, s.stream));
+    a.ovf_count = reinterpret_cast<uint32_t*>(w);
+    a.ovf_list = reinterpret_cast<uint32_t*>(w + 256);
+    a.gheap = w + 256 + size_t(s.nq) * 4;
+    a.gheap = reinterpret_cast<uint8_t*>((reinterpret_cast<uintptr_t>(a.gheap) + 15) & ~uintptr_t(15));
+    a.gheap_cap = int(gcap);
+    a2.ovf_count = a.ovf_count;
+    a2.ovf_list = a.ovf_list;
+    a2.gheap = a.gheap;
+    a2.gheap_cap = a.gheap_cap;
+    a2.heap_cap = a.heap_cap;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, a.ovf_count);
+
     const int64_t grid = std::min<int64_t>(s.nq, int64_t(1) << 30);
     if (!is_f32) {
-        hipLaunchKernelGGL(k_search<MODE_U8>, dim3(unsigned(grid)), dim3(WAVE), lds_bytes, s.stream, a);
+        if (idx->row_bytes == 128)
+            launch_kpl<MODE_U8, 8>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
+        else
+            launch_kpl<MODE_U8, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
     } else if (bf16) {
-        hipLaunchKernelGGL(k_search<MODE_BF16>, dim3(unsigned(grid)), dim3(WAVE), lds_bytes, s.stream, a);
+        launch_kpl<MODE_BF16, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
     } else {
-        hipLaunchKernelGGL(k_search<MODE_F32>, dim3(unsigned(grid)), dim3(WAVE), lds_bytes, s.stream, a);
+        launch_kpl<MODE_F32, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
     }
     ANN_HIP_CHECK(hipGetLastError());
+    ANN_HIP_CHECK(hipFreeAsync(w, s.stream));
     return ANN_OK;
 }
 

@@ -146,7 +146,7 @@ class Index:
                       precision: int = 0, rerank_k: int = 0, out=None, stats=None, trace=None, stream=None):
         """Device search on torch tensors, asynchronous on `stream` (default: current).
 
-        Returns (ids, dists) tensors of shape nq x k.  `stats` (nq x 8 int32) and
+        Returns (ids, dists) tensors of shape nq x k.  `stats` (nq x 12 int32) and
         `trace` (nq x budget int32) are optional output tensors."""
         import torch
         nq = queries.shape[0]

@@ -73,7 +73,7 @@ WORKLOADS = {
     # 1M x 128 u8, 256 components; R=16, P=4 x 32 dims, K=32 (1,048,576
     # bridges); t=100, b=5 as in the paper's bridge-graph construction.
     "sift_like_1m_u8": Workload("sift_like_1m_u8", 1_000_000, 128, "u8", 256, 10_000, 16, 4, 32,
-                                10, (128, 512, 2048, 4096, 8192, 16384),
+                                10, (128, 256, 512, 1024, 2048, 4096, 8192, 16384),
                                 bridge_t=100, bridge_b=5, seed_base=2),
     # 1M x 384 f32 GIST-like; R=16, P=3 x 128 dims, K=100 (10^6 bridges).
     "gist_like_1m_f32": Workload("gist_like_1m_f32", 1_000_000, 384, "f32", 128, 1_000, 16, 3,

@@ -24,7 +24,7 @@ def gpu_search(idx, Q, k, T, L=64, ks=None, Ts=None, trace=False, stats=False, p
     qd = torch.from_numpy(np.ascontiguousarray(Q)).cuda()
     nq = Q.shape[0]
     tr = torch.empty((nq, max(T, 1)), dtype=torch.int32, device="cuda") if trace else None
-    st = torch.empty((nq, 8), dtype=torch.int32, device="cuda") if stats else None
+    st = torch.empty((nq, 12), dtype=torch.int32, device="cuda") if stats else None
     kd = None if ks is None else torch.from_numpy(np.asarray(ks, np.int32)).cuda()
     td = None if Ts is None else torch.from_numpy(np.asarray(Ts, np.int32)).cuda()
     ids, dd = _index_cls().search_device(idx, qd, k, T, ks=kd, budgets=td, queue_len=L, trace=tr, stats=st,
