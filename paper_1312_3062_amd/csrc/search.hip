@@ -311,56 +311,54 @@ __device__ inline uint64_t reg_get(const uint64_t (&v)[KPL], int e) {
     return r;
 }
 
-// Merge the keys of the lanes with `isnew` (distinct, none present) into the
-// sorted array v[h .. h+n), keep the `cap` smallest, leave them in v[0..).
-// Same result as offering the keys one by one to a bounded set that evicts
-// its largest key when full.
+// Whole-wave lane shifts of a 64-bit value (DPP wave_shr:1 / wave_shl:1).
+// shr: lane i receives lane i-1, lane 0 receives `fill`.
+// shl: lane i receives lane i+1, lane 63 receives `fill`.
+__device__ inline uint64_t wave_shr1(uint64_t v, uint64_t fill) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill)), int(uint32_t(v)), 0x138, 0xF, 0xF, false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill >> 32)), int(uint32_t(v >> 32)), 0x138, 0xF, 0xF, false));
+    return (uint64_t(hi) << 32) | lo;
+}
+__device__ inline uint64_t wave_shl1(uint64_t v, uint64_t fill) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill)), int(uint32_t(v)), 0x130, 0xF, 0xF, false));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(int(uint32_t(fill >> 32)), int(uint32_t(v >> 32)), 0x130, 0xF, 0xF, false));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Offer the keys of the lanes with `isnew` (distinct, none present) to the
+// sorted array v[0..n) of capacity cap: each one goes to its rank and the
+// tail moves up one place; at capacity the largest key falls off.  Same
+// result as a bounded set that evicts its largest key when full.
 template <int KPL>
-__device__ inline void reg_merge(uint64_t (&v)[KPL], int& h, int& n, int cap, uint64_t x, bool isnew,
-                                 uint64_t* scratch, int lane) {
+__device__ inline void reg_insert(uint64_t (&v)[KPL], int& n, int cap, uint64_t x, bool isnew, int lane) {
     uint64_t nm = __ballot(isnew);
-    const int m = __popcll(nm);
-    int c_old[KPL];
-#pragma unroll
-    for (int u = 0; u < KPL; ++u) c_old[u] = 0;
-    int rank_new = 0, c_new = 0;
     while (nm) {
         const int j = __builtin_ctzll(nm);
         nm &= nm - 1;
         const uint64_t xj = readlane64(x, j);
-        int cnt = 0;
+        if (n == cap && xj > reg_get<KPL>(v, n - 1)) continue;
+        int pos = 0;
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) pos += __popcll(__ballot(lane + u * WAVE < n && v[u] < xj));
+        uint64_t carry = KEY_EMPTY;  // lane 63 of the previous register
 #pragma unroll
         for (int u = 0; u < KPL; ++u) {
+            const uint64_t next_carry = readlane64(v[u], WAVE - 1);
+            const uint64_t sh = wave_shr1(v[u], carry);
             const int e = lane + u * WAVE;
-            const bool live = e >= h && e < h + n;
-            c_old[u] += (live && xj < v[u]) ? 1 : 0;
-            cnt += __popcll(__ballot(live && v[u] < xj));
+            v[u] = e < pos ? v[u] : (e == pos ? xj : sh);
+            carry = next_carry;
         }
-        rank_new += xj < x ? 1 : 0;
-        if (lane == j) c_new = cnt;
+        if (n < cap) ++n;
     }
-    const int total = min(cap, n + m);
-#pragma unroll
-    for (int u = 0; u < KPL; ++u) {
-        const int e = lane + u * WAVE;
-        if (e >= h && e < h + n) {
-            const int pos = e - h + c_old[u];
-            if (pos < total) scratch[pos] = v[u];
-        }
-    }
-    if (isnew) {
-        const int pos = rank_new + c_new;
-        if (pos < total) scratch[pos] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < KPL; ++u) {
-        const int e = lane + u * WAVE;
-        v[u] = e < total ? scratch[e] : KEY_EMPTY;
-    }
-    __syncthreads();
-    h = 0;
-    n = total;
+}
+
+// remove and return the smallest key (n > 0)
+__device__ inline uint64_t reg_pop_front(uint64_t (&v)[1], int& n) {
+    const uint64_t x = readlane64(v[0], 0);
+    v[0] = wave_shl1(v[0], KEY_EMPTY);
+    --n;
+    return x;
 }
 
 template <int MODE, int NC16, int KPL, bool RERUN>
@@ -441,11 +439,11 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         int ring_h = 0, ring_n = 0;
         uint64_t bkey = KEY_EMPTY;  // next non-empty bridge (ring head)
         uint64_t Qv[1] = {KEY_EMPTY};
-        int qh = 0, qn = 0;
+        int qn = 0;
         uint64_t Rv[KPL];
 #pragma unroll
         for (int u = 0; u < KPL; ++u) Rv[u] = KEY_EMPTY;
-        int rh = 0, rn = 0;
+        int rn = 0;
         // look-ahead rows: lane l holds neighbour (l % R) of entry (l / R)
         uint32_t acn = ID_EMPTY;  // lane s < S: node id of entry s
         uint32_t ac_id = ID_EMPTY, ac_d = 0;
@@ -460,10 +458,10 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             if (a.trace && ev) a.trace[qi * a.Tmax + t + r] = int32_t(key_id(key));
             const uint64_t rworst = rn < rcap ? KEY_EMPTY : reg_get<KPL>(Rv, rn - 1);
             const bool ra = ev && key < rworst;
-            if (__ballot(ra)) reg_merge<KPL>(Rv, rh, rn, rcap, key, ra, scratch, lane);
-            const uint64_t qworst = qn < a.L ? KEY_EMPTY : readlane64(Qv[0], qh + qn - 1);
+            if (__ballot(ra)) reg_insert<KPL>(Rv, rn, rcap, key, ra, lane);
+            const uint64_t qworst = qn < a.L ? KEY_EMPTY : readlane64(Qv[0], qn - 1);
             const bool qa = ev && key < qworst;
-            if (__ballot(qa)) reg_merge<1>(Qv, qh, qn, a.L, key, qa, scratch, lane);
+            if (__ballot(qa)) reg_insert<1>(Qv, qn, a.L, key, qa, lane);
         };
 
         while (t < T) {
@@ -532,9 +530,13 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             if (flags) break;
 
             // ---- which vertex Alg. 1 pops next: the queue head or the next bridge
-            const uint64_t qkey = qn > 0 ? readlane64(Qv[0], qh) : KEY_EMPTY;
+            const uint64_t qkey = qn > 0 ? readlane64(Qv[0], 0) : KEY_EMPTY;
             const bool use_bridge = ring_h < ring_n && bkey < qkey;
             if (!use_bridge && qn == 0) break;  // queue empty and every bridge consumed
+            if (!use_bridge && key_id(qkey) >= uint32_t(n)) {  // never happens: keys hold evaluated ids
+                flags = ANN_ERESOURCE;
+                break;
+            }
 
             bool ev = false, full = false;
             uint32_t id = ID_EMPTY, dist = 0;
@@ -555,7 +557,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     const int ns = min(S, qn);
                     acn = ID_EMPTY;
                     for (int s = 0; s < ns; ++s) {
-                        const uint32_t nd = key_id(readlane64(Qv[0], qh + s));
+                        const uint32_t nd = key_id(readlane64(Qv[0], s));
                         if (lane == s) acn = nd;
                     }
                     ac_id = ID_EMPTY;
@@ -582,8 +584,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     hit = 1;  // entry 0 is the queue head
                 }
                 const int s = __builtin_ctzll(hit);
-                ++qh;
-                --qn;
+                reg_pop_front(Qv, qn);
                 ++st_rpop;
                 // ---- expand: the row sits in lanes [s*R, s*R + R)
                 const bool inrow = R > 0 && row_lane_slot == s && lane < (s + 1) * R;
@@ -714,7 +715,6 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             s[ANN_STAT_LOOKAHEADS + 2] = 0;
             s[ANN_STAT_LOOKAHEADS + 3] = 0;
         }
-        (void)rh;
         __syncthreads();
     }
 }
@@ -751,7 +751,7 @@ __global__ void __launch_bounds__(WAVE) k_tables(const void* Q, int64_t nq, int 
 int align_up(int v, int a) { return (v + a - 1) / a * a; }
 
 // LDS layout of one query's state; the heap is left out for the re-run kernel
-int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap) {
+int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf16, int lpr) {
     int off = 0;
     auto take = [&](int bytes, int al) {
         off = align_up(off, al);
@@ -765,16 +765,17 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap) {
     a.o_perm = take(PK, 8);
     a.o_hk = with_heap ? take(a.heap_cap * 8, 8) : 0;
     a.o_hr = with_heap ? take(a.heap_cap * 4, 8) : 0;
-    a.o_rk = take(WAVE * 8, 8);
-    a.o_ro = take(WAVE * 4, 8);
-    a.o_rl = take(WAVE * 4, 8);
-    a.o_sk = take(WAVE * 8, 8);
+    a.o_rk = take(GEN_BATCH * 8, 8);
+    a.o_ro = take(GEN_BATCH * 4, 8);
+    a.o_rl = take(GEN_BATCH * 4, 8);
+    a.o_sk = take(GEN_BATCH * 8, 8);
     a.o_hash = take(int(a.hash_buckets) * 16, 16);
     a.o_dck = take(int(a.dc_buckets) * 16, 16);
     a.o_dcv = take(int(a.dc_buckets) * 16, 16);
-    a.o_scr = take(std::max(std::max(a.L, rcap), WAVE) * 8, 8);
-    a.o_gid = take(std::max(WAVE, rcap * 2) * 4, 8);  // also holds the re-rank keys
-    a.o_gd = take(WAVE * 4, 8);
+    // re-rank keys (bf16) and the row list of multi-lane gathers (fp32, bf16)
+    a.o_scr = take(bf16 ? rcap * 8 : 8, 8);
+    a.o_gid = take(bf16 ? std::max(WAVE * 4, rcap * 8) : (lpr > 1 ? WAVE * 4 : 8), 8);
+    a.o_gd = take(lpr > 1 ? WAVE * 4 : 8, 8);
     a.o_sc = take(16 * 4, 8);
     return align_up(off, 16);
 }
@@ -843,15 +844,16 @@ int launch_search(const SearchLaunch& s) {
     a.dc_buckets = 128;  // distance cache: 512 slots, cleared when half full
     a.spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     // LDS frontier of the multi-sequence; larger ones go to the re-run kernel
-    a.heap_cap = int(std::min<int64_t>(idx->nb, 320));
+    a.heap_cap = int(std::min<int64_t>(idx->nb, 192));
 
     const int qbytes = is_f32 ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
     const int rcap = bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
     ANN_REQUIRE(rcap <= 1024, "search: k (or rerank_k) above 1024");
     SearchArgs a2 = a;
-    const int lds1 = layout(a, qbytes, PK, rcap, true);
-    const int lds2 = layout(a2, qbytes, PK, rcap, false);
+    const int lpr = is_f32 ? (bf16 ? Traits<MODE_BF16>::LPR : Traits<MODE_F32>::LPR) : Traits<MODE_U8>::LPR;
+    const int lds1 = layout(a, qbytes, PK, rcap, true, bf16, lpr);
+    const int lds2 = layout(a2, qbytes, PK, rcap, false, bf16, lpr);
 
     int dev = 0, max_lds = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
