@@ -42,7 +42,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sift_like_1m_u8")
-    ap.add_argument("--budget", type=int, default=0, help="fixed budget T (0: smallest grid T with recall >= 0.9)")
+    ap.add_argument("--budget", type=int, default=0,
+                    help="fixed budget T (0: the smallest budget on the refined grid with recall >= target)")
     ap.add_argument("--target-recall", type=float, default=0.9)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -84,7 +85,7 @@ def main():
     grid = [args.budget] if args.budget else list(w.budgets)
     sweep = []
     chosen = None
-    for T in grid:
+    def run(T):
         ids, dd = idx.search_device(qd, w.k, T, queue_len=w.queue_len, stats=stats)
         torch.cuda.synchronize()
         st = stats.cpu().numpy()
@@ -93,10 +94,25 @@ def main():
         rec = recall_at(ids.cpu().numpy(), gt, w.k)
         sweep.append({"budget": T, "recall@10": round(rec, 4)})
         log(f"[bench] T={T} recall@{w.k}={rec:.4f} evals={st[:, 0].mean():.0f} ref_pops={st[:, 1].mean():.0f} "
-            f"bridge_pops={st[:, 2].mean():.0f} bridges_gen={st[:, 4].mean():.0f} heap_max={st[:, 5].max()}")
-        chosen = (T, rec, st)
-        if rec >= args.target_recall:
+            f"bridge_pops={st[:, 2].mean():.0f} bridges_gen={st[:, 4].mean():.0f} heap_max={st[:, 5].max()} "
+            f"rows={st[:, 7].mean():.0f} lookaheads={st[:, 8].mean():.0f}")
+        return T, rec, st
+
+    # doubling grid first, then the smallest budget reaching the target
+    # between the last two grid points, in steps of an eighth of the lower one
+    prev = None
+    for T in grid:
+        chosen = run(T)
+        if chosen[1] >= args.target_recall:
             break
+        prev = T
+    if not args.budget and prev is not None and chosen[1] >= args.target_recall:
+        step = max(16, prev // 8)
+        for T in range(prev + step, chosen[0], step):
+            c = run(T)
+            if c[1] >= args.target_recall:
+                chosen = c
+                break
     T, rec, st = chosen
 
     # timed region: K whole-batch searches, HIP events on the launch stream
