@@ -119,21 +119,30 @@ def main():
     stream = torch.cuda.current_stream()
     out = (torch.empty((nq, w.k), dtype=torch.int32, device="cuda"),
            torch.empty((nq, w.k), dtype=torch.int32 if X.dtype == np.uint8 else torch.float32, device="cuda"))
-    for _ in range(args.warmup):
-        idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out)
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    t_wall = time.perf_counter()
-    for a, b in ev:
-        a.record(stream)
-        idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out)
-        b.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
+
+    def timed(tune):
+        for _ in range(args.warmup):
+            idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out, tune=tune)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        t_wall = time.perf_counter()
+        for a, b in ev:
+            a.record(stream)
+            idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out, tune=tune)
+            b.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_wall
+        return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+    plain_wall, plain_kms = timed(None)
+    log(f"[bench] plain launch: {plain_kms:.3f} ms kernel, {nq * args.steps / plain_wall:.0f} QPS")
+    tune = idx.autotune(qd, w.k, T, queue_len=w.queue_len)
+    log(f"[bench] autotuned launch setting: {tune}")
+    wall, kms = timed(tune)
     ms_step = wall * 1000.0 / args.steps
     qps = nq * args.steps / wall
-    kms = float(np.mean(kern_ms))
+    log(f"[bench] tuned launch: {kms:.3f} ms kernel, {qps:.0f} QPS")
 
     d_bytes = X.shape[1] * X.itemsize
     B = algorithmic_bytes(st, d_bytes, w.graph_k, w.k, d_bytes)
@@ -172,7 +181,8 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": w.d, "queries": nq, "k": w.k, "budget": T,
                    "queue_len": w.queue_len, "graph_k": w.graph_k, "P": w.P, "K": w.K,
                    "bridge_t": w.bridge_t, "bridge_b": w.bridge_b, "recall@10": round(rec, 4),
-                   "budget_sweep": sweep, "kernel": "plain", "build_s": round(build_s, 2)},
+                   "budget_sweep": sweep, "launch": tune, "build_s": round(build_s, 2),
+                   "plain_qps": round(nq * args.steps / plain_wall, 1), "plain_kernel_ms": round(plain_kms, 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                      "kernel": "k_search", "kernel_ms": round(kms, 4),

@@ -100,12 +100,28 @@ typedef struct {
  *  precision  ann_precision (ignored for u8).
  *  rerank_k   ANN_PRECISION_BF16_RERANK only: how many of the best bf16
  *             candidates are re-ranked in fp32 (0 means k).
+ * Launch tuning (results never depend on these; 0 = library default):
+ *  lookahead     queue entries whose kNN rows are loaded and whose
+ *                neighbours are measured together, 1..8 (default: as many
+ *                as 64 lanes hold, 64 / graph_k).
+ *  persistent    1: a grid of resident wavefronts drains a device work
+ *                counter instead of one workgroup per query.
+ *  waves_per_cu  persistent only: resident wavefronts per compute unit
+ *                (default: as many as fit).
+ *  order         persistent with per-query budgets: 1 serves the queries
+ *                in descending budget (powers of two), longest first.
+ * A caller built against the first version (struct_size 16, no tuning
+ * fields) is accepted and gets the defaults.
  */
 typedef struct {
     uint32_t struct_size; /* sizeof(ann_search_params) */
     int32_t queue_len;
     int32_t precision;
     int32_t rerank_k;
+    int32_t lookahead;
+    int32_t persistent;
+    int32_t waves_per_cu;
+    int32_t order;
 } ann_search_params;
 
 typedef struct {
@@ -225,6 +241,33 @@ int ann_search(const ann_index* idx, const void* queries, int64_t nq, int32_t k,
 int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
                       const int32_t* d_k, const int32_t* d_budget, const ann_search_params* params,
                       int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
+
+/*
+ * Device workspace that ann_search_device_ws needs for this request (bytes).
+ */
+int ann_search_workspace_size(const ann_index* idx, int64_t nq, int32_t k, int32_t budget,
+                              const ann_search_params* params, int64_t* bytes);
+
+/*
+ * ann_search_device with a caller-provided device workspace (16-byte aligned,
+ * at least ann_search_workspace_size bytes): the call allocates nothing, so
+ * it can be captured into a graph and replayed.  The workspace is owned by
+ * the caller and must not be shared by launches that overlap in time.
+ */
+int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                         const int32_t* d_k, const int32_t* d_budget, const ann_search_params* params,
+                         int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* workspace,
+                         int64_t workspace_bytes, void* stream);
+
+/*
+ * Launch autotuner: times the launch-tuning choices of ann_search_params
+ * (lookahead, persistent, waves_per_cu, order) on the given device batch
+ * and writes the fastest into *params; the other fields are kept.  Every
+ * candidate must return the same ids; a difference is reported as
+ * ANN_ESTATE.  Synchronous on `stream`.
+ */
+int ann_autotune(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                 const int32_t* d_k, const int32_t* d_budget, ann_search_params* params, void* stream);
 
 /*
  * Query preprocessing alone (Sec. 4.2): for each query the P x K squared

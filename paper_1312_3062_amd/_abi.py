@@ -27,7 +27,8 @@ class BuildParams(C.Structure):
 
 class SearchParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("queue_len", C.c_int32), ("precision", C.c_int32),
-                ("rerank_k", C.c_int32)]
+                ("rerank_k", C.c_int32), ("lookahead", C.c_int32), ("persistent", C.c_int32),
+                ("waves_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
 class IndexInfo(C.Structure):
@@ -57,6 +58,10 @@ SIGNATURES = {
     "ann_search": (_i32, [_vp, _vp, _i64, _i32, _i32, C.POINTER(SearchParams), _vp, _vp]),
     "ann_search_device": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp, _vp, _vp,
                                  _vp, _vp]),
+    "ann_search_workspace_size": (_i32, [_vp, _i64, _i32, _i32, C.POINTER(SearchParams), C.POINTER(_i64)]),
+    "ann_search_device_ws": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp, _vp, _vp,
+                                    _vp, _vp, _i64, _vp]),
+    "ann_autotune": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp]),
     "ann_query_tables_device": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "ann_knn_device": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "ann_last_error": (_cp, []),

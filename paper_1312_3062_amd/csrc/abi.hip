@@ -373,6 +373,9 @@ int ann_index_load(const char* path, ann_index** out) {
 
 void ann_index_free(ann_index* idx) { free_index(idx); }
 
+// struct_size of the first version of ann_search_params (no tuning fields)
+static constexpr uint32_t kSearchParamsV1 = 16;
+
 static int check_search(const ann_index* idx, int64_t nq, int32_t k, int32_t budget, const ann_search_params* sp) {
     ANN_REQUIRE(idx, "search: null index");
     ANN_REQUIRE(nq >= 0, "search: nq must be >= 0");
@@ -380,21 +383,25 @@ static int check_search(const ann_index* idx, int64_t nq, int32_t k, int32_t bud
     ANN_REQUIRE(budget >= 0, "search: budget must be >= 0");
     ANN_REQUIRE(budget <= (1 << 20), "search: budget above 2^20");
     if (sp) {
-        ANN_REQUIRE(sp->struct_size == sizeof(ann_search_params), "ann_search_params.struct_size mismatch");
+        ANN_REQUIRE(sp->struct_size == sizeof(ann_search_params) || sp->struct_size == kSearchParamsV1,
+                    "ann_search_params.struct_size mismatch");
         ANN_REQUIRE(sp->queue_len >= 1 && sp->queue_len <= 64, "queue_len must be in [1, 64]");
         ANN_REQUIRE(sp->precision == ANN_PRECISION_EXACT || sp->precision == ANN_PRECISION_BF16_RERANK,
                     "unknown precision");
         ANN_REQUIRE(sp->rerank_k >= 0 && sp->rerank_k <= 1024, "rerank_k must be in [0, 1024]");
+        if (sp->struct_size == sizeof(ann_search_params)) {
+            ANN_REQUIRE(sp->lookahead >= 0 && sp->lookahead <= 8, "lookahead must be in [0, 8]");
+            ANN_REQUIRE(sp->persistent == 0 || sp->persistent == 1, "persistent must be 0 or 1");
+            ANN_REQUIRE(sp->waves_per_cu >= 0 && sp->waves_per_cu <= 64, "waves_per_cu must be in [0, 64]");
+            ANN_REQUIRE(sp->order == 0 || sp->order == 1, "order must be 0 or 1");
+        }
     }
     return ANN_OK;
 }
 
-int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
-                      const int32_t* d_k, const int32_t* d_budget, const ann_search_params* sp, int32_t* d_ids,
-                      void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream) {
-    int rc = check_search(idx, nq, k, budget, sp);
-    if (rc) return rc;
-    ANN_REQUIRE(nq == 0 || (d_queries && d_ids && d_dists), "search: null device buffer");
+static SearchLaunch make_launch(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                                const int32_t* d_k, const int32_t* d_budget, const ann_search_params* sp,
+                                int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream) {
     SearchLaunch a{};
     a.idx = idx;
     a.d_q = d_queries;
@@ -411,7 +418,126 @@ int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, i
     a.d_stats = d_stats;
     a.d_trace = d_trace;
     a.stream = static_cast<hipStream_t>(stream);
+    if (sp && sp->struct_size == sizeof(ann_search_params)) {
+        a.lookahead = sp->lookahead;
+        a.persistent = sp->persistent;
+        a.waves_per_cu = sp->waves_per_cu;
+        a.order = sp->order;
+    }
+    return a;
+}
+
+int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                      const int32_t* d_k, const int32_t* d_budget, const ann_search_params* sp, int32_t* d_ids,
+                      void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    ANN_REQUIRE(nq == 0 || (d_queries && d_ids && d_dists), "search: null device buffer");
+    return launch_search(make_launch(idx, d_queries, nq, k, budget, d_k, d_budget, sp, d_ids, d_dists, d_stats,
+                                     d_trace, stream));
+}
+
+int ann_search_workspace_size(const ann_index* idx, int64_t nq, int32_t k, int32_t budget,
+                              const ann_search_params* sp, int64_t* bytes) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    ANN_REQUIRE(bytes, "ann_search_workspace_size: null output");
+    return search_workspace_bytes(
+        make_launch(idx, nullptr, nq, k, budget, nullptr, nullptr, sp, nullptr, nullptr, nullptr, nullptr, nullptr),
+        bytes);
+}
+
+int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                         const int32_t* d_k, const int32_t* d_budget, const ann_search_params* sp, int32_t* d_ids,
+                         void* d_dists, int32_t* d_stats, int32_t* d_trace, void* workspace, int64_t workspace_bytes,
+                         void* stream) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    ANN_REQUIRE(nq == 0 || (d_queries && d_ids && d_dists), "search: null device buffer");
+    ANN_REQUIRE(nq == 0 || workspace, "ann_search_device_ws: null workspace");
+    SearchLaunch a =
+        make_launch(idx, d_queries, nq, k, budget, d_k, d_budget, sp, d_ids, d_dists, d_stats, d_trace, stream);
+    a.workspace = workspace;
+    a.workspace_bytes = workspace_bytes;
     return launch_search(a);
+}
+
+int ann_autotune(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                 const int32_t* d_k, const int32_t* d_budget, ann_search_params* sp, void* stream) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    ANN_REQUIRE(sp && sp->struct_size == sizeof(ann_search_params), "ann_autotune: params of the current version");
+    ANN_REQUIRE(nq > 0 && d_queries, "ann_autotune: empty batch");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t ob = size_t(nq) * k * 4;
+    void *di = nullptr, *dd = nullptr;
+    ANN_HIP_CHECK(hipMalloc(&di, ob));
+    ANN_HIP_CHECK(hipMalloc(&dd, ob));
+    struct Free {
+        void** p[2];
+        ~Free() {
+            for (void** q : p)
+                if (*q) (void)hipFree(*q);
+        }
+    } guard{{&di, &dd}};
+    hipEvent_t e0, e1;
+    ANN_HIP_CHECK(hipEventCreate(&e0));
+    ANN_HIP_CHECK(hipEventCreate(&e1));
+    std::vector<int32_t> ref(size_t(nq) * k), got(size_t(nq) * k);
+    const int max_spec = idx->R > 0 ? std::min(8, 64 / idx->R) : 1;
+    std::vector<int> specs = {max_spec};
+    for (int v : {1, 2, 4})
+        if (v < max_spec) specs.push_back(v);
+    std::vector<ann_search_params> cands;
+    for (int spec : specs) {
+        ann_search_params c = *sp;
+        c.lookahead = spec;
+        c.persistent = 0;
+        c.waves_per_cu = 0;
+        c.order = 0;
+        cands.push_back(c);
+        for (int wpc : {0, 8, 4}) {
+            for (int ord : {0, 1}) {
+                if (ord && !d_budget) continue;
+                ann_search_params p = c;
+                p.persistent = 1;
+                p.waves_per_cu = wpc;
+                p.order = ord;
+                cands.push_back(p);
+            }
+        }
+    }
+    float best = 1e30f;
+    ann_search_params best_p = cands[0];
+    for (size_t i = 0; i < cands.size(); ++i) {
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            ANN_HIP_CHECK(hipEventRecord(e0, st));
+            rc = ann_search_device(idx, d_queries, nq, k, budget, d_k, d_budget, &cands[i], static_cast<int32_t*>(di),
+                                   dd, nullptr, nullptr, stream);
+            if (rc) return rc;
+            ANN_HIP_CHECK(hipEventRecord(e1, st));
+            ANN_HIP_CHECK(hipEventSynchronize(e1));
+            float t = 0.f;
+            ANN_HIP_CHECK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
+        ANN_HIP_CHECK(hipMemcpy(i == 0 ? ref.data() : got.data(), di, ob, hipMemcpyDeviceToHost));
+        if (i > 0 && got != ref)
+            return set_error(ANN_ESTATE, "ann_autotune: a launch setting changed the results (candidate " +
+                                             std::to_string(i) + ")");
+        if (ms < best) {
+            best = ms;
+            best_p = cands[i];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    sp->lookahead = best_p.lookahead;
+    sp->persistent = best_p.persistent;
+    sp->waves_per_cu = best_p.waves_per_cu;
+    sp->order = best_p.order;
+    return ANN_OK;
 }
 
 int ann_search(const ann_index* idx, const void* queries, int64_t nq, int32_t k, int32_t budget,

@@ -38,9 +38,17 @@ struct SearchLaunch {
     int32_t* d_stats;
     int32_t* d_trace;
     hipStream_t stream;
+    // launch tuning (never changes results)
+    int lookahead = 0;      // queue entries whose rows are loaded together (0: as many as fit)
+    int persistent = 0;     // resident grid draining a work counter
+    int waves_per_cu = 0;   // persistent: resident workgroups per CU (0: all that fit)
+    int order = 0;          // persistent with per-query budgets: longest first
+    void* workspace = nullptr;  // caller-provided workspace (null: allocated on the stream)
+    int64_t workspace_bytes = 0;
 };
 
 int launch_search(const SearchLaunch& a);
+int search_workspace_bytes(const SearchLaunch& a, int64_t* bytes);
 int launch_tables(const ann_index* idx, const void* d_q, int64_t nq, void* d_sorted, int32_t* d_perm,
                   hipStream_t s);
 int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, int64_t nq, int k, int exclude_self,

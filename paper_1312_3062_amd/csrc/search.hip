@@ -73,6 +73,8 @@ struct SearchArgs {
     uint32_t* ovf_count;
     uint8_t* gheap;      // re-run kernel: per-workgroup heap in global memory
     int gheap_cap;
+    uint32_t* work_counter;  // persistent launch: next work item (null: grid-stride)
+    const uint32_t* perm;    // optional serving order of the queries
     // LDS layout (byte offsets)
     int o_q, o_tab, o_sv, o_perm, o_hk, o_hr, o_rk, o_ro, o_rl, o_sk, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd, o_sc;
 };
@@ -407,8 +409,19 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     const int row_lane_j = R > 0 ? lane % R : 0;
 
     const int64_t nwork = RERUN ? int64_t(*a.ovf_count) : a.nq;
-    for (int64_t wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
-        const int64_t qi = RERUN ? int64_t(a.ovf_list[wi]) : wi;
+    // persistent launch: every workgroup takes the next item of a device
+    // counter until the batch is drained; otherwise grid-stride
+    const bool persistent = !RERUN && a.work_counter != nullptr;
+    auto grab = [&]() -> int64_t {
+        if (lane == 0) sc[3] = int(atomicAdd(a.work_counter, 1u));
+        __syncthreads();
+        const int64_t v = sc[3];
+        __syncthreads();
+        return v;
+    };
+    for (int64_t wi = persistent ? grab() : int64_t(blockIdx.x); wi < nwork;
+         wi = persistent ? grab() : wi + gridDim.x) {
+        const int64_t qi = RERUN ? int64_t(a.ovf_list[wi]) : (a.perm ? int64_t(a.perm[wi]) : wi);
         // per-query values are clamped to the launch maxima that sized the buffers
         const int k = a.ks ? min(max(a.ks[qi], 1), a.kmax) : a.kmax;
         const int T = a.Ts ? min(max(a.Ts[qi], 0), a.Tmax) : a.Tmax;
@@ -719,8 +732,37 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     }
 }
 
-__global__ void k_zero_u32(uint32_t* p) {
-    if (threadIdx.x == 0) *p = 0;
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// Serving order for uneven budgets: queries bucketed by descending budget
+// (powers of two), so the longest ones start first.  Any order gives the same
+// results; this one shortens the tail of a persistent launch.
+__device__ inline int budget_bucket(int T) { return 20 - min(20, 31 - __clz(max(T, 1))); }
+
+__global__ void k_order_count(const int32_t* Ts, int64_t nq, uint32_t* counts) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nq) atomicAdd(&counts[budget_bucket(Ts[i])], 1u);
+}
+
+__global__ void k_order_scan(uint32_t* counts) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int b = 0; b < 32; ++b) {
+        const uint32_t c = counts[b];
+        counts[b] = run;
+        run += c;
+    }
+}
+
+__global__ void k_order_scatter(const int32_t* Ts, int64_t nq, const uint32_t* start, uint32_t* cursor,
+                                uint32_t* perm) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nq) {
+        const int b = budget_bucket(Ts[i]);
+        perm[start[b] + atomicAdd(&cursor[b], 1u)] = uint32_t(i);
+    }
 }
 
 // standalone tables kernel (query preprocessing only)
@@ -780,40 +822,66 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
     return align_up(off, 16);
 }
 
+struct Grid {
+    int64_t grid;     // workgroups of the main launch (0: derive from occupancy)
+    int waves_per_cu; // persistent: cap on resident workgroups per CU (0: all that fit)
+    int cus;
+};
+
 template <int MODE, int NC16, int KPL>
-void launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, int64_t grid, int grid2,
-                 hipStream_t st) {
-    hipLaunchKernelGGL((k_search<MODE, NC16, KPL, false>), dim3(unsigned(grid)), dim3(WAVE), lds1, st, a1);
+int launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, Grid g, int grid2,
+                hipStream_t st) {
+    auto* k1 = k_search<MODE, NC16, KPL, false>;
+    int64_t grid = g.grid;
+    if (a1.work_counter) {
+        int per_cu = 0;
+        ANN_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k1, WAVE, lds1));
+        per_cu = std::max(1, per_cu);
+        if (g.waves_per_cu > 0) per_cu = std::min(per_cu, g.waves_per_cu);
+        grid = std::min<int64_t>(a1.nq, int64_t(per_cu) * g.cus);
+    }
+    hipLaunchKernelGGL(k1, dim3(unsigned(grid)), dim3(WAVE), lds1, st, a1);
     hipLaunchKernelGGL((k_search<MODE, NC16, KPL, true>), dim3(unsigned(grid2)), dim3(WAVE), lds2, st, a2);
+    return ANN_OK;
 }
 
 template <int MODE, int NC16>
-void launch_kpl(int rcap, const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, int64_t grid, int grid2,
-                hipStream_t st) {
-    if (rcap <= 64)
-        launch_mode<MODE, NC16, 1>(a1, a2, lds1, lds2, grid, grid2, st);
-    else if (rcap <= 128)
-        launch_mode<MODE, NC16, 2>(a1, a2, lds1, lds2, grid, grid2, st);
-    else
-        launch_mode<MODE, NC16, 16>(a1, a2, lds1, lds2, grid, grid2, st);
+int launch_kpl(int rcap, const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, Grid g, int grid2,
+               hipStream_t st) {
+    if (rcap <= 64) return launch_mode<MODE, NC16, 1>(a1, a2, lds1, lds2, g, grid2, st);
+    if (rcap <= 128) return launch_mode<MODE, NC16, 2>(a1, a2, lds1, lds2, g, grid2, st);
+    return launch_mode<MODE, NC16, 16>(a1, a2, lds1, lds2, g, grid2, st);
 }
 
 }  // namespace
 
-int launch_search(const SearchLaunch& s) {
+// Everything about a search launch that follows from the index and the
+// request: kernel arguments, LDS layout and the workspace it needs.
+struct Plan {
+    SearchArgs a, a2;
+    int lds1 = 0, lds2 = 0, rcap = 0;
+    bool bf16 = false, is_f32 = false;
+    int grid2 = 64;
+    int64_t gcap = 0;
+    size_t ws_bytes = 0;
+};
+
+static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
+
+static int make_plan(const SearchLaunch& s, Plan& pl) {
     const ann_index* idx = s.idx;
-    if (s.nq == 0) return ANN_OK;
     ANN_REQUIRE(idx->R <= WAVE, "search: graph out-degree above 64 is not supported");
-    SearchArgs a{};
-    const bool is_f32 = idx->dtype == ANN_F32;
-    const bool bf16 = is_f32 && s.precision == ANN_PRECISION_BF16_RERANK;
-    if (bf16) {
+    SearchArgs& a = pl.a;
+    a = SearchArgs{};
+    pl.is_f32 = idx->dtype == ANN_F32;
+    pl.bf16 = pl.is_f32 && s.precision == ANN_PRECISION_BF16_RERANK;
+    if (pl.bf16) {
         ANN_REQUIRE(idx->Xbf16 != nullptr, "bf16 copy of the vectors is missing");
         ANN_REQUIRE(idx->d % 8 == 0, "bf16 precision needs d divisible by 8");
     }
-    a.X = bf16 ? reinterpret_cast<const uint8_t*>(idx->Xbf16) : idx->X;
+    a.X = pl.bf16 ? reinterpret_cast<const uint8_t*>(idx->Xbf16) : idx->X;
     a.Xf32 = idx->X;
-    a.row_bytes = bf16 ? int64_t(idx->d) * 2 : idx->row_bytes;
+    a.row_bytes = pl.bf16 ? int64_t(idx->d) * 2 : idx->row_bytes;
     a.row_bytes_f32 = idx->row_bytes;
     a.n = idx->n;
     a.d = idx->d;
@@ -842,58 +910,105 @@ int launch_search(const SearchLaunch& s) {
     // than it evaluates); buckets for a final load of about 0.75
     a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 4 / 3 / 4 + 1));
     a.dc_buckets = 128;  // distance cache: 512 slots, cleared when half full
-    a.spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
+    const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
+    a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
     // LDS frontier of the multi-sequence; larger ones go to the re-run kernel
     a.heap_cap = int(std::min<int64_t>(idx->nb, 192));
 
-    const int qbytes = is_f32 ? idx->d * 4 : idx->d;
+    const int qbytes = pl.is_f32 ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
-    const int rcap = bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
-    ANN_REQUIRE(rcap <= 1024, "search: k (or rerank_k) above 1024");
-    SearchArgs a2 = a;
-    const int lpr = is_f32 ? (bf16 ? Traits<MODE_BF16>::LPR : Traits<MODE_F32>::LPR) : Traits<MODE_U8>::LPR;
-    const int lds1 = layout(a, qbytes, PK, rcap, true, bf16, lpr);
-    const int lds2 = layout(a2, qbytes, PK, rcap, false, bf16, lpr);
+    pl.rcap = pl.bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
+    ANN_REQUIRE(pl.rcap <= 1024, "search: k (or rerank_k) above 1024");
+    pl.a2 = a;
+    const int lpr = pl.is_f32 ? (pl.bf16 ? Traits<MODE_BF16>::LPR : Traits<MODE_F32>::LPR) : Traits<MODE_U8>::LPR;
+    pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+    pl.lds2 = layout(pl.a2, qbytes, PK, pl.rcap, false, pl.bf16, lpr);
 
-    int dev = 0, max_lds = 0;
+    // workspace: counters | overflow list | order buckets | order | re-run heaps
+    pl.gcap = std::min<int64_t>(idx->nb, std::max<int64_t>(4096, 8 * int64_t(s.Tmax) + 1024));
+    pl.ws_bytes = 256 + round16(size_t(s.nq) * 4) + 256 + round16(size_t(s.nq) * 4) +
+                  size_t(pl.grid2) * size_t(pl.gcap) * 12;
+    return ANN_OK;
+}
+
+int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes) {
+    Plan pl;
+    int rc = make_plan(s, pl);
+    if (rc) return rc;
+    *bytes = int64_t(pl.ws_bytes);
+    return ANN_OK;
+}
+
+int launch_search(const SearchLaunch& s) {
+    if (s.nq == 0) return ANN_OK;
+    Plan pl;
+    int rc = make_plan(s, pl);
+    if (rc) return rc;
+    SearchArgs& a = pl.a;
+    SearchArgs& a2 = pl.a2;
+
+    int dev = 0, max_lds = 0, cus = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (lds1 > max_lds)
-        return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(lds1) +
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (pl.lds1 > max_lds)
+        return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(pl.lds1) +
                                                " bytes of LDS per query, more than the device's " +
                                                std::to_string(max_lds) + " (lower budget or k)");
 
-    // re-run workspace: overflow list, its counter, one global heap per workgroup
-    const int grid2 = 64;
-    const int64_t gcap = std::min<int64_t>(idx->nb, std::max<int64_t>(4096, 8 * int64_t(s.Tmax) + 1024));
-    const size_t ws = size_t(s.nq) * 4 + 256 + 16 + size_t(grid2) * size_t(gcap) * 12;
-    uint8_t* w = nullptr;
-    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), ws, s.stream));
-    a.ovf_count = reinterpret_cast<uint32_t*>(w);
-    a.ovf_list = reinterpret_cast<uint32_t*>(w + 256);
-    a.gheap = w + 256 + size_t(s.nq) * 4;
-    a.gheap = reinterpret_cast<uint8_t*>((reinterpret_cast<uintptr_t>(a.gheap) + 15) & ~uintptr_t(15));
-    a.gheap_cap = int(gcap);
-    a2.ovf_count = a.ovf_count;
-    a2.ovf_list = a.ovf_list;
-    a2.gheap = a.gheap;
-    a2.gheap_cap = a.gheap_cap;
-    a2.heap_cap = a.heap_cap;
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, a.ovf_count);
-
-    const int64_t grid = std::min<int64_t>(s.nq, int64_t(1) << 30);
-    if (!is_f32) {
-        if (idx->row_bytes == 128)
-            launch_kpl<MODE_U8, 8>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
-        else
-            launch_kpl<MODE_U8, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
-    } else if (bf16) {
-        launch_kpl<MODE_BF16, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
+    uint8_t* w = static_cast<uint8_t*>(s.workspace);
+    const bool own = w == nullptr;
+    if (own) {
+        ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), pl.ws_bytes, s.stream));
     } else {
-        launch_kpl<MODE_F32, 0>(rcap, a, a2, lds1, lds2, grid, grid2, s.stream);
+        ANN_REQUIRE(s.workspace_bytes >= int64_t(pl.ws_bytes), "search: workspace too small");
+        ANN_REQUIRE((reinterpret_cast<uintptr_t>(w) & 15) == 0, "search: workspace must be 16-byte aligned");
     }
+    uint32_t* counters = reinterpret_cast<uint32_t*>(w);  // [0] overflow count, [1] work counter
+    size_t o = 256;
+    uint32_t* ovf_list = reinterpret_cast<uint32_t*>(w + o);
+    o += round16(size_t(s.nq) * 4);
+    uint32_t* buckets = reinterpret_cast<uint32_t*>(w + o);  // 32 starts + 32 cursors
+    o += 256;
+    uint32_t* perm = reinterpret_cast<uint32_t*>(w + o);
+    o += round16(size_t(s.nq) * 4);
+    uint8_t* gheap = w + o;
+
+    a.ovf_count = a2.ovf_count = counters;
+    a.ovf_list = a2.ovf_list = ovf_list;
+    a.gheap = a2.gheap = gheap;
+    a.gheap_cap = a2.gheap_cap = int(pl.gcap);
+    a2.heap_cap = a.heap_cap;
+    a.work_counter = s.persistent ? counters + 1 : nullptr;
+    a2.work_counter = nullptr;
+    a.perm = nullptr;
+    // counters and order buckets are cleared by a kernel (no memset nodes in captured graphs)
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, counters, 64);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, buckets, 64);
+    if (s.persistent && s.order && s.d_T) {
+        const unsigned gb = unsigned(ceil_div(s.nq, 256));
+        hipLaunchKernelGGL(k_order_count, dim3(gb), dim3(256), 0, s.stream, s.d_T, s.nq, buckets);
+        hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(WAVE), 0, s.stream, buckets);
+        hipLaunchKernelGGL(k_order_scatter, dim3(gb), dim3(256), 0, s.stream, s.d_T, s.nq, buckets, buckets + 32,
+                           perm);
+        a.perm = perm;
+    }
+
+    const Grid g{std::min<int64_t>(s.nq, int64_t(1) << 30), s.waves_per_cu, cus};
+    const ann_index* idx = s.idx;
+    if (!pl.is_f32) {
+        if (idx->row_bytes == 128)
+            rc = launch_kpl<MODE_U8, 8>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+        else
+            rc = launch_kpl<MODE_U8, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+    } else if (pl.bf16) {
+        rc = launch_kpl<MODE_BF16, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+    } else {
+        rc = launch_kpl<MODE_F32, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+    }
+    if (rc) return rc;
     ANN_HIP_CHECK(hipGetLastError());
-    ANN_HIP_CHECK(hipFreeAsync(w, s.stream));
+    if (own) ANN_HIP_CHECK(hipFreeAsync(w, s.stream));
     return ANN_OK;
 }
 

@@ -48,8 +48,15 @@ def _stream_ptr(stream=None) -> Optional[C.c_void_p]:
     return C.c_void_p(s.cuda_stream)
 
 
-def search_params(queue_len: int = 64, precision: int = 0, rerank_k: int = 0) -> _abi.SearchParams:
-    return _abi.SearchParams(C.sizeof(_abi.SearchParams), queue_len, precision, rerank_k)
+TUNING_KEYS = ("lookahead", "persistent", "waves_per_cu", "order")
+
+
+def search_params(queue_len: int = 64, precision: int = 0, rerank_k: int = 0, tune: Optional[dict] = None
+                  ) -> _abi.SearchParams:
+    """ann_search_params; `tune` holds launch-tuning fields (results never depend on them)."""
+    t = tune or {}
+    return _abi.SearchParams(C.sizeof(_abi.SearchParams), queue_len, precision, rerank_k,
+                             *(int(t.get(key, 0)) for key in TUNING_KEYS))
 
 
 class Index:
@@ -143,11 +150,14 @@ class Index:
         return ids, dists
 
     def search_device(self, queries, k: int, budget: int, ks=None, budgets=None, queue_len: int = 64,
-                      precision: int = 0, rerank_k: int = 0, out=None, stats=None, trace=None, stream=None):
+                      precision: int = 0, rerank_k: int = 0, out=None, stats=None, trace=None, stream=None,
+                      tune: Optional[dict] = None, workspace=None):
         """Device search on torch tensors, asynchronous on `stream` (default: current).
 
         Returns (ids, dists) tensors of shape nq x k.  `stats` (nq x 12 int32) and
-        `trace` (nq x budget int32) are optional output tensors."""
+        `trace` (nq x budget int32) are optional output tensors.  `tune` holds
+        launch settings (see TUNING_KEYS).  With `workspace` (a uint8 device
+        tensor of at least workspace_bytes(...)) the call allocates nothing."""
         import torch
         nq = queries.shape[0]
         dev = queries.device
@@ -157,11 +167,31 @@ class Index:
                              device=dev)
         else:
             ids, dd = out
-        sp = search_params(queue_len, precision, rerank_k)
-        check(lib().ann_search_device(self._h, _tptr(queries), nq, k, budget, _tptr(ks), _tptr(budgets),
-                                      C.byref(sp), _tptr(ids), _tptr(dd), _tptr(stats), _tptr(trace),
-                                      _stream_ptr(stream)))
+        sp = search_params(queue_len, precision, rerank_k, tune)
+        if workspace is None:
+            check(lib().ann_search_device(self._h, _tptr(queries), nq, k, budget, _tptr(ks), _tptr(budgets),
+                                          C.byref(sp), _tptr(ids), _tptr(dd), _tptr(stats), _tptr(trace),
+                                          _stream_ptr(stream)))
+        else:
+            check(lib().ann_search_device_ws(self._h, _tptr(queries), nq, k, budget, _tptr(ks), _tptr(budgets),
+                                             C.byref(sp), _tptr(ids), _tptr(dd), _tptr(stats), _tptr(trace),
+                                             _tptr(workspace), workspace.numel(), _stream_ptr(stream)))
         return ids, dd
+
+    def workspace_bytes(self, nq: int, k: int, budget: int, queue_len: int = 64, precision: int = 0,
+                        rerank_k: int = 0, tune: Optional[dict] = None) -> int:
+        sp = search_params(queue_len, precision, rerank_k, tune)
+        out = C.c_int64()
+        check(lib().ann_search_workspace_size(self._h, nq, k, budget, C.byref(sp), C.byref(out)))
+        return out.value
+
+    def autotune(self, queries, k: int, budget: int, ks=None, budgets=None, queue_len: int = 64,
+                 precision: int = 0, rerank_k: int = 0, stream=None) -> dict:
+        """Time the launch settings on this batch; returns the fastest as a `tune` dict."""
+        sp = search_params(queue_len, precision, rerank_k)
+        check(lib().ann_autotune(self._h, _tptr(queries), queries.shape[0], k, budget, _tptr(ks), _tptr(budgets),
+                                 C.byref(sp), _stream_ptr(stream)))
+        return {key: getattr(sp, key) for key in TUNING_KEYS}
 
     def tables_device(self, queries, stream=None):
         """(sorted values, codeword of each rank) per query, shapes nq x P x K."""
