@@ -36,6 +36,58 @@ def algorithmic_bytes(stats: np.ndarray, d_bytes: int, R: int, k: int, query_byt
     return evals * d_bytes + rpop * 4 * R + bgen * 8 + bids * 4 + query_bytes + 8 * k
 
 
+def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
+    """Poisson request streams at fractions of the plain saturation rate, served
+    (continuous batching) and plain (one launch per request).  With fixed_k /
+    fixed_budget every request uses them (the recall >= 0.9 operating point);
+    otherwise k and the budget vary per request."""
+    from paper_1312_3062_amd import recall_at, synth
+    from paper_1312_3062_amd.serve import Server
+
+    def stream(rate, off):
+        rs = synth.request_stream(w, args.serve_pool, rate, seed_offset=off)
+        for r in rs:
+            if fixed_k:
+                r.k = fixed_k
+            if fixed_budget:
+                r.budget = fixed_budget
+        return rs
+
+    pool = synth.queries(w, nq=args.serve_pool)
+    srv = Server(idx, w.d, "u8" if w.dtype == "u8" else "f32", slots=4, slot_queries=4096, kmax=100,
+                 queue_len=w.queue_len)
+    probe = stream(1.0, 99)[:120]
+    srv.run_served(probe[:20], pool)  # warm-up of both paths
+    srv.run_plain(probe[:20], pool)
+    svc = srv.plain_service_time(probe, pool)
+    sat = 1.0 / svc
+    log(f"[serve] plain service time {svc * 1e3:.2f} ms/request -> saturation {sat:.1f} requests/s")
+    runs, checks = [], {}
+    for i, f in enumerate((0.5, 0.8, 1.1)):
+        reqs = stream(f * sat, i)[:args.serve_requests]
+        keep = f == 0.8
+        a = srv.run_served(reqs, pool, f * sat, keep_ids=keep)
+        b = srv.run_plain(reqs, pool, f * sat, keep_ids=keep)
+        for r in (a, b):
+            sm = r.summary()
+            sm["load"] = f
+            runs.append(sm)
+            log(f"[serve] load {f:.1f}x {sm['mode']:6s}: {sm['qps']:.0f} QPS, p50 {sm['p50_ms']:.2f} ms, "
+                f"p99 {sm['p99_ms']:.2f} ms, {sm['launches']} launches")
+        if keep:
+            checks["mix_invariant"] = bool(np.array_equal(a.ids, b.ids))
+            nq = a.ids.shape[0]
+            kq = np.concatenate([[r.k] * r.batch for r in reqs])
+            sel = np.nonzero(kq >= 10)[0]
+            gt = gt_fn(pool[:nq][sel])
+            checks["recall@10_k>=10"] = round(recall_at(a.ids[sel], gt, 10), 4)
+            log(f"[serve] same ids served and plain: {checks['mix_invariant']}; "
+                f"recall@10 over {len(sel)} queries with k>=10: {checks['recall@10_k>=10']}")
+    return {"index": w.name, "k": fixed_k or "1|10|100", "budget": fixed_budget or "128..8192",
+            "requests_per_run": args.serve_requests, "plain_service_ms": round(svc * 1e3, 3),
+            "plain_saturation_rps": round(sat, 2), "runs": runs, **checks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,6 +99,11 @@ def main():
     ap.add_argument("--target-recall", type=float, default=0.9)
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-vs-plain request streams")
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per served / plain run")
+    ap.add_argument("--serve-mixed", action="store_true",
+                    help="also serve a stream with k in {1,10,100} and budgets 128..8192 per request")
+    ap.add_argument("--serve-pool", type=int, default=200_000, help="query vectors the request streams draw")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -150,6 +207,20 @@ def main():
     log(f"[bench] T={T}: {ms_step:.3f} ms/step wall, kernel {kms:.3f} ms, QPS {qps:.0f}, "
         f"algorithmic {B.sum() / 1e9:.3f} GB/launch -> {achieved:.1f} GB/s")
 
+    serving = None
+    if not args.no_serve:
+        xd2 = torch.from_numpy(X).cuda()
+
+        def gt_fn(qs):
+            ids_, _ = knn_device(xd2, torch.from_numpy(np.ascontiguousarray(qs)).cuda(), 10)
+            torch.cuda.synchronize()
+            return ids_.cpu().numpy()
+
+        serving = {"operating_point": serving_leg(idx, w, args, gt_fn, fixed_k=w.k, fixed_budget=T)}
+        if args.serve_mixed:
+            serving["mixed_k_budget"] = serving_leg(idx, w, args, gt_fn)
+        del xd2
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -188,6 +259,7 @@ def main():
                      "kernel": "k_search", "kernel_ms": round(kms, 4),
                      "algorithmic_bytes_per_launch": int(B.sum())},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(line), flush=True)
 
