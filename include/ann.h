@@ -149,7 +149,12 @@ enum {
     ANN_STAT_FLAGS = 6,        /* 0, or ANN_ERESOURCE if a structure overflowed */
     ANN_STAT_ROWS = 7,         /* vector rows gathered, look-ahead included */
     ANN_STAT_LOOKAHEADS = 8,   /* batches of kNN rows loaded ahead */
-    ANN_NSTATS = 12            /* 9..11 reserved, written as 0 */
+    ANN_STAT_RERUN = 9,        /* 1 if the query was searched again by the re-run kernel
+                                  (its multi-sequence outgrew LDS and no global slot was
+                                  free) */
+    ANN_STAT_MOVED = 10,       /* 1 if the multi-sequence outgrew LDS and carried on in a
+                                  global slot of the workspace */
+    ANN_NSTATS = 12            /* 11 reserved, written as 0 */
 };
 
 /* ------------------------------------------------------------------ */
@@ -243,16 +248,21 @@ int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, i
                       int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
 
 /*
- * Device workspace that ann_search_device_ws needs for this request (bytes).
+ * Device workspace for ann_search_device_ws and this request (bytes): the
+ * per-query lists plus 256 global slots for multi-sequence state that
+ * outgrows LDS.
  */
 int ann_search_workspace_size(const ann_index* idx, int64_t nq, int32_t k, int32_t budget,
                               const ann_search_params* params, int64_t* bytes);
 
 /*
- * ann_search_device with a caller-provided device workspace (16-byte aligned,
- * at least ann_search_workspace_size bytes): the call allocates nothing, so
- * it can be captured into a graph and replayed.  The workspace is owned by
- * the caller and must not be shared by launches that overlap in time.
+ * ann_search_device with a caller-provided device workspace (16-byte aligned):
+ * the call allocates nothing, so it can be captured into a graph and
+ * replayed.  The workspace is owned by the caller and must not be shared by
+ * launches that overlap in time.  A workspace smaller than
+ * ann_search_workspace_size holds fewer global slots (at least one must
+ * fit, else ANN_EINVAL); queries that find no free slot are searched again
+ * by a second kernel, with the same results.
  */
 int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
                          const int32_t* d_k, const int32_t* d_budget, const ann_search_params* params,

@@ -16,7 +16,7 @@ ANN_OK, ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ESTATE, ANN_EUNSUPPORTED, ANN_E
 PRECISION_EXACT, PRECISION_BF16_RERANK = 0, 1
 NSTATS = 12
 STAT_NAMES = ("evals", "ref_pops", "bridge_pops", "bridge_ids", "bridges_gen", "heap_max", "flags", "rows",
-              "lookaheads", "reserved9", "reserved10", "reserved11")
+              "lookaheads", "rerun", "moved", "reserved11")
 
 
 class BuildParams(C.Structure):

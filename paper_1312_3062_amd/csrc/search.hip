@@ -43,6 +43,7 @@ enum { MODE_U8 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 
 constexpr int GEN_BATCH = 32;  // bridges extracted per look-ahead step
 constexpr int MAX_SPEC = 8;    // references whose rows are loaded ahead together
+constexpr int PRE_LIST = 8;    // bridge lists up to this length are fetched with the bridge
 
 struct SearchArgs {
     const uint8_t* X;     // rows that drive the search (u8, f32 or bf16)
@@ -68,15 +69,19 @@ struct SearchArgs {
     uint32_t hash_buckets;  // visited set: buckets of 4 slots
     uint32_t dc_buckets;    // distance cache: buckets of 4 slots
     int spec;               // S, references loaded ahead (S * R <= 64)
-    int heap_cap;
+    int ms_cap;             // multi-sequence: materialised side and outer frontier capacity
+    int prefetch;           // fetch short bridge lists (and distances) with the bridges
     uint32_t* ovf_list;  // queries whose LDS heap overflowed
     uint32_t* ovf_count;
-    uint8_t* gheap;      // re-run kernel: per-workgroup heap in global memory
-    int gheap_cap;
+    uint8_t* gheap;      // multi-sequence state in global memory: nslots slots of gms_cap
+    int gms_cap;         // capacity of a slot
+    int nslots;          // slots; the re-run kernel's workgroup b owns slot b
+    uint32_t* slot_bits; // main kernel: bitmap of the slots in use (cleared at launch)
     uint32_t* work_counter;  // persistent launch: next work item (null: grid-stride)
     const uint32_t* perm;    // optional serving order of the queries
     // LDS layout (byte offsets)
-    int o_q, o_tab, o_sv, o_perm, o_hk, o_hr, o_rk, o_ro, o_rl, o_sk, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd, o_sc;
+    int o_q, o_sv, o_perm, o_ms, o_rk, o_ro, o_rl, o_sk, o_pid, o_pd, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd,
+        o_sc;
 };
 
 template <int MODE>
@@ -363,19 +368,190 @@ __device__ inline uint64_t reg_pop_front(uint64_t (&v)[1], int& n) {
     return x;
 }
 
+// ------------------------------------------------------------------
+// Pairwise multi-sequence (Sec. 3.3), driven by one lane.
+//
+// The P sorted subspace lists are split into two sides: X = lists {0} or
+// {0,1}, Y = the rest ({}, {1}, {2} or {2,3}).  A side of two lists is
+// enumerated lazily by its own 2-list multi-sequence and its elements kept in
+// order ("materialised"); a side of one list is that list.  The outer 2-list
+// enumeration over (X, Y) yields the bridges in (sum, lid) order: every list
+// is sorted by (value, codeword), each side by (sum, lid) with lid the
+// concatenated codewords, and a tuple's unique parent -- (i, j-1), or (i-1, 0)
+// when j = 0 -- always precedes it in that order.  The outer frontier holds
+// at most one entry per row of X, so it grows with the square root of the
+// bridges extracted, not with their number.
+// ------------------------------------------------------------------
+struct MSeqMem {
+    uint64_t* mx;   // materialised X elements: sum << 32 | lid
+    uint64_t* my;   // materialised Y elements
+    uint64_t* hxk;  // inner heap of X: keys, ranks (ra << 8 | rb)
+    uint32_t* hxr;
+    uint64_t* hyk;  // inner heap of Y
+    uint32_t* hyr;
+    uint64_t* hok;  // outer heap: keys sum << 32 | n + lid, positions i << 16 | j
+    uint32_t* hor;
+    int cap;        // capacity of mx, my and hok
+};
+
+__host__ __device__ inline int mseq_bytes(int cap, int K) {
+    const int ocap = cap + K + 1;
+    return cap * 8 * 2 + ocap * 12 + (K + 1) * 12 * 2 + 64;
+}
+
+// a global slot: mseq_bytes rounded up so that every slot starts 64-byte aligned
+__host__ __device__ inline int mseq_slot_bytes(int cap, int K) { return (mseq_bytes(cap, K) + 63) & ~63; }
+
+__device__ inline MSeqMem mseq_carve(uint8_t* base, int cap, int K) {
+    MSeqMem m;
+    const int ocap = cap + K + 1;
+    m.mx = reinterpret_cast<uint64_t*>(base);
+    m.my = m.mx + cap;
+    m.hok = m.my + cap;
+    m.hxk = m.hok + ocap;
+    m.hyk = m.hxk + (K + 1);
+    m.hor = reinterpret_cast<uint32_t*>(m.hyk + (K + 1));
+    m.hxr = m.hor + ocap;
+    m.hyr = m.hxr + (K + 1);
+    m.cap = cap;
+    return m;
+}
+
+// Constant part of the enumeration (the same in every lane).
+struct MSeqConf {
+    const uint32_t* sv;
+    const uint8_t* perm;
+    int K;
+    uint32_t n;
+    int nx, ny;           // lists on each side
+    int ax, bx, ay, by;   // their subspaces
+    uint32_t sizeX, sizeY;
+    MSeqMem m;
+};
+
+__device__ inline MSeqConf mseq_conf(const uint32_t* sv, const uint8_t* perm, int P, int K, uint32_t n, MSeqMem m) {
+    MSeqConf c;
+    c.sv = sv;
+    c.perm = perm;
+    c.K = K;
+    c.n = n;
+    c.m = m;
+    c.nx = P >= 3 ? 2 : 1;
+    c.ny = P - c.nx;
+    c.ax = 0;
+    c.bx = 1;
+    c.ay = c.nx;
+    c.by = c.nx + 1;
+    c.sizeX = c.nx == 2 ? uint32_t(K * K) : uint32_t(K);
+    c.sizeY = c.ny == 2 ? uint32_t(K * K) : (c.ny == 1 ? uint32_t(K) : 1u);
+    return c;
+}
+
+// Changing part, driven by one lane.
+template <bool FLOAT>
+struct PairMSeq {
+    int cx, cy, hxn, hyn, hon, maxf;
+    bool of;  // a structure outgrew its capacity
+
+    __device__ static uint32_t add(uint32_t s1, uint32_t s2) {
+        if constexpr (FLOAT)
+            return f_bits(bits_f(s1) + bits_f(s2));
+        else
+            return s1 + s2;
+    }
+    __device__ static uint64_t inner_key(const MSeqConf& c, int a, int b, uint32_t ra, uint32_t rb) {
+        const uint32_t sum = add(c.sv[a * c.K + ra], c.sv[b * c.K + rb]);
+        return make_key(sum, uint32_t(c.perm[a * c.K + ra]) * uint32_t(c.K) + c.perm[b * c.K + rb]);
+    }
+    // element e of a side, materialising it if needed
+    __device__ bool elem(const MSeqConf& c, bool isx, uint32_t e, uint32_t& sum, uint32_t& lid) {
+        const int nl = isx ? c.nx : c.ny;
+        const int la = isx ? c.ax : c.ay, lb = isx ? c.bx : c.by;
+        if (nl == 0) {
+            sum = 0;
+            lid = 0;
+            return true;
+        }
+        if (nl == 1) {
+            sum = c.sv[la * c.K + e];
+            lid = c.perm[la * c.K + e];
+            return true;
+        }
+        int& cnt = isx ? cx : cy;
+        int& hn = isx ? hxn : hyn;
+        uint64_t* M = isx ? c.m.mx : c.m.my;
+        uint64_t* hk = isx ? c.m.hxk : c.m.hyk;
+        uint32_t* hr = isx ? c.m.hxr : c.m.hyr;
+        while (uint32_t(cnt) <= e) {
+            if (hn == 0) return false;
+            if (cnt >= c.m.cap) {
+                of = true;
+                return false;
+            }
+            uint64_t key;
+            uint32_t rk;
+            heap_pop(hk, hr, hn, key, rk);
+            M[cnt++] = key;
+            const uint32_t ra = rk >> 8, rb = rk & 0xFF;
+            if (rb + 1 < uint32_t(c.K)) heap_push(hk, hr, hn, inner_key(c, la, lb, ra, rb + 1), (ra << 8) | (rb + 1));
+            if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hk, hr, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
+        }
+        sum = key_dist(M[e]);
+        lid = key_id(M[e]);
+        return true;
+    }
+    __device__ void outer_push(const MSeqConf& c, uint32_t i, uint32_t j) {
+        uint32_t sx, lx, sy, ly;
+        if (!elem(c, true, i, sx, lx) || !elem(c, false, j, sy, ly)) return;
+        if (hon >= c.m.cap + c.K + 1) {
+            of = true;
+            return;
+        }
+        heap_push(c.m.hok, c.m.hor, hon, make_key(add(sx, sy), c.n + lx * c.sizeY + ly), (i << 16) | j);
+        maxf = max(maxf, hon);
+    }
+    // the next call of next() may need an element or frontier entry beyond
+    // the capacity (it adds at most one element to each side and one entry to
+    // the frontier: a pushed position is at most one past the elements its
+    // parent used)
+    __device__ bool tight(const MSeqConf& c) const {
+        const bool x = c.nx == 2 && cx >= c.m.cap && uint32_t(cx) < c.sizeX;
+        const bool y = c.ny == 2 && cy >= c.m.cap && uint32_t(cy) < c.sizeY;
+        return x || y || hon + 2 > c.m.cap + c.K + 1;
+    }
+    __device__ void init(const MSeqConf& c) {
+        cx = cy = hxn = hyn = hon = maxf = 0;
+        of = false;
+        if (c.nx == 2) heap_push(c.m.hxk, c.m.hxr, hxn, inner_key(c, c.ax, c.bx, 0, 0), 0u);
+        if (c.ny == 2) heap_push(c.m.hyk, c.m.hyr, hyn, inner_key(c, c.ay, c.by, 0, 0), 0u);
+        outer_push(c, 0, 0);
+    }
+    // the next bridge in (distance, lid) order; false when exhausted or overflowed
+    __device__ bool next(const MSeqConf& c, uint64_t& key) {
+        if (hon == 0 || of) return false;
+        uint32_t pos;
+        heap_pop(c.m.hok, c.m.hor, hon, key, pos);
+        const uint32_t i = pos >> 16, j = pos & 0xFFFF;
+        if (j + 1 < c.sizeY) outer_push(c, i, j + 1);
+        if (j == 0 && i + 1 < c.sizeX) outer_push(c, i + 1, 0);
+        return true;
+    }
+};
+
 template <int MODE, int NC16, int KPL, bool RERUN>
 __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr bool FLOAT = Traits<MODE>::FLOAT;
 
     uint8_t* qv = lds + a.o_q;
-    uint32_t* tab = reinterpret_cast<uint32_t*>(lds + a.o_tab);
     uint32_t* sv = reinterpret_cast<uint32_t*>(lds + a.o_sv);
     uint8_t* perm = lds + a.o_perm;
     uint64_t* ring_key = reinterpret_cast<uint64_t*>(lds + a.o_rk);
     uint32_t* ring_off = reinterpret_cast<uint32_t*>(lds + a.o_ro);
     uint32_t* ring_len = reinterpret_cast<uint32_t*>(lds + a.o_rl);
     uint64_t* stage = reinterpret_cast<uint64_t*>(lds + a.o_sk);
+    uint32_t* pre_id = reinterpret_cast<uint32_t*>(lds + a.o_pid);  // prefetched bridge lists, 8 per entry
+    uint32_t* pre_d = reinterpret_cast<uint32_t*>(lds + a.o_pd);    // and their distances
     uint32_t* H = reinterpret_cast<uint32_t*>(lds + a.o_hash);
     uint32_t* DK = reinterpret_cast<uint32_t*>(lds + a.o_dck);
     uint32_t* DV = reinterpret_cast<uint32_t*>(lds + a.o_dcv);
@@ -384,18 +560,12 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     uint32_t* gd = reinterpret_cast<uint32_t*>(lds + a.o_gd);
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
 
-    uint64_t* hk;
-    uint32_t* hr;
-    int heap_cap;
-    if constexpr (RERUN) {
-        hk = reinterpret_cast<uint64_t*>(a.gheap + int64_t(blockIdx.x) * a.gheap_cap * 12);
-        hr = reinterpret_cast<uint32_t*>(hk + a.gheap_cap);
-        heap_cap = a.gheap_cap;
-    } else {
-        hk = reinterpret_cast<uint64_t*>(lds + a.o_hk);
-        hr = reinterpret_cast<uint32_t*>(lds + a.o_hr);
-        heap_cap = a.heap_cap;
-    }
+    const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, a.K);
+    MSeqMem msm;
+    if constexpr (RERUN)
+        msm = mseq_carve(a.gheap + int64_t(blockIdx.x) * slot_bytes, a.gms_cap, a.K);
+    else
+        msm = mseq_carve(lds + a.o_ms, a.ms_cap, a.K);
 
     const int lane = lane_id();
     const int64_t n = a.n;
@@ -427,29 +597,30 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         const int T = a.Ts ? min(max(a.Ts[qi], 0), a.Tmax) : a.Tmax;
         const int rcap = (MODE == MODE_BF16) ? max(k, a.rerank_k) : k;
 
-        // ---- load the query, clear the visited set and the distance cache
+        // ---- load the query, clear the distance cache
         {
             const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(a.Q) + qi * qbytes);
             uint32_t* dst = reinterpret_cast<uint32_t*>(qv);
             for (int i = lane; i < qbytes / 4; i += WAVE) dst[i] = src[i];
-            for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
             for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
         }
         __syncthreads();
 
-        // ---- tables and their sort; the nearest bridge seeds the frontier
-        compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, tab, sv, perm, lane);
-        if (lane == 0) {
-            int hn = 0;
-            heap_push(hk, hr, hn, tuple_key<FLOAT>(0u, sv, perm, P, K, n), 0u);
-            sc[0] = hn;
-        }
+        // ---- tables and their sort (the raw tables use the visited set's
+        //      memory, cleared afterwards); the nearest bridge seeds the frontier
+        compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, H, sv, perm, lane);
+        for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
         __syncthreads();
-
-        int heap_n = sc[0];
-        int heap_max = heap_n;
+        MSeqConf msc = mseq_conf(sv, perm, P, K, uint32_t(n), msm);
+        PairMSeq<FLOAT> ms;
+        if (lane == 0) ms.init(msc);
+        int slot = -1;  // global slot the enumeration moved to (main kernel)
+        bool ms_alive = true;  // the enumeration can still yield bridges
+        int heap_max = 1;
         int flags = 0;
         int ring_h = 0, ring_n = 0;
+        int refills = 0;
+        uint32_t ids_mask = 0, dist_mask = 0;  // ring entries with prefetched ids / distances
         uint64_t bkey = KEY_EMPTY;  // next non-empty bridge (ring head)
         uint64_t Qv[1] = {KEY_EMPTY};
         int qn = 0;
@@ -478,42 +649,37 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         };
 
         while (t < T) {
-            // ---- look-ahead extraction of the next non-empty bridges
+            // ---- look-ahead extraction of the next non-empty bridges; their
+            //      lists (and, once bridges are in use, their distances) are
+            //      fetched with them: the bridge order does not depend on the
+            //      traversal
             if (ring_h == ring_n) {
-                while (ring_h == ring_n && heap_n > 0 && flags == 0) {
+                while (ring_h == ring_n && ms_alive && flags == 0) {
                     if (lane == 0) {
-                        int hn = heap_n, g = 0, of = 0;
-                        for (; g < GEN_BATCH && hn > 0; ++g) {
-                            uint64_t key;
-                            uint32_t rk;
-                            heap_pop(hk, hr, hn, key, rk);
-                            stage[g] = key;
-                            // unique-parent rule: raise one rank at or after the last non-zero one
-                            int last = 0;
-                            for (int p = 0; p < P; ++p)
-                                if ((rk >> (8 * p)) & 0xFF) last = p;
-                            for (int b = last; b < P; ++b) {
-                                const int r = (rk >> (8 * b)) & 0xFF;
-                                if (r + 1 >= K) continue;
-                                if (hn >= heap_cap) {
-                                    of = 1;
-                                    break;
-                                }
-                                const uint32_t crk = rk + (1u << (8 * b));
-                                heap_push(hk, hr, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, n), crk);
-                            }
-                            if (of) {
-                                ++g;
+                        // batches of 4, 8, 16, then 32 bridges: at small budgets a
+                        // query expands about one bridge
+                        const int gb = min(GEN_BATCH, 4 << min(refills, 3));
+                        int g = 0;
+                        uint64_t key;
+                        bool move = false;
+                        while (g < gb) {
+                            if (!RERUN && slot < 0 && ms.tight(msc)) {
+                                move = true;  // continue from a global slot
                                 break;
                             }
+                            if (!ms.next(msc, key)) break;
+                            stage[g++] = key;
                         }
-                        sc[0] = hn;
-                        sc[1] = of;
+                        sc[0] = (ms.hon > 0 && !ms.of) ? 1 : 0;
+                        sc[1] = ms.of ? 1 : 0;
                         sc[2] = g;
+                        sc[4] = ms.maxf;
+                        sc[5] = move ? 1 : 0;
                     }
                     __syncthreads();
-                    heap_n = sc[0];
-                    heap_max = max(heap_max, heap_n);
+                    const bool move = sc[5] != 0;
+                    ms_alive = sc[0] != 0;
+                    heap_max = sc[4];
                     const int g = sc[2];
                     if (sc[1]) flags = ANN_ERESOURCE;
                     st_gen += g;
@@ -528,15 +694,107 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                         ne = o1 > o0;
                     }
                     const uint64_t mask = __ballot(ne);
+                    const int pos = lanes_below(mask);
                     if (ne) {
-                        const int pos = lanes_below(mask);
                         ring_key[pos] = key;
                         ring_off[pos] = o0;
                         ring_len[pos] = o1 - o0;
                     }
                     ring_h = 0;
                     ring_n = __popcll(mask);
+                    // short lists: ids now, from the second refill on also distances
+                    if (a.prefetch) {
+                        // bit e: ring entry e (rank of its lane among the non-empty ones) is short
+                        const uint64_t sm = __ballot(ne && o1 - o0 <= uint32_t(PRE_LIST));
+                        uint32_t mk = 0;
+                        uint64_t bits = sm;
+                        while (bits) {
+                            const int l = __builtin_ctzll(bits);
+                            bits &= bits - 1;
+                            mk |= 1u << __popcll(mask & ((uint64_t(1) << l) - 1));
+                        }
+                        ids_mask = mk;
+                    }
                     __syncthreads();
+                    ++refills;
+                    const bool with_dist = refills >= 2;
+#pragma unroll 1
+                    for (int u = 0; a.prefetch && u < GEN_BATCH * PRE_LIST / WAVE; ++u) {
+                        const int sl = lane + u * WAVE;
+                        const int e = sl / PRE_LIST, x = sl % PRE_LIST;
+                        uint32_t pid = ID_EMPTY;
+                        if (e < ring_n && ((ids_mask >> e) & 1u) && uint32_t(x) < ring_len[e])
+                            pid = a.bids[ring_off[e] + x];
+                        pre_id[sl] = pid;
+                        if (with_dist) {
+                            bool need = false;
+                            uint32_t d = 0;
+                            if (pid != ID_EMPTY && set_find(H, a.hash_buckets, pid) < 0) {
+                                const int ds = set_find(DK, a.dc_buckets, pid);
+                                if (ds >= 0)
+                                    d = DV[ds];
+                                else
+                                    need = true;
+                            }
+                            const uint32_t gdist = gather_need<MODE, NC16>(a, qv, pid, need, gid, gd, lane);
+                            st_rows += __popcll(__ballot(need));
+                            pre_d[sl] = need ? gdist : d;
+                        }
+                    }
+                    dist_mask = with_dist ? ids_mask : 0u;
+                    __syncthreads();
+                    if constexpr (!RERUN) {
+                        if (move) {
+                            // the LDS state is full: claim a free global slot and
+                            // carry on there (no free slot: the re-run kernel
+                            // redoes the query)
+                            if (lane == 0) {
+                                int got = -1;
+                                for (int tries = 0; tries < 4 * a.nslots && got < 0; ++tries) {
+                                    const int w = (int(blockIdx.x) + tries) % ((a.nslots + 31) / 32);
+                                    const uint32_t used = __hip_atomic_load(a.slot_bits + w, __ATOMIC_RELAXED,
+                                                                            __HIP_MEMORY_SCOPE_AGENT);
+                                    const int nb = min(32, a.nslots - 32 * w);
+                                    const uint32_t freeb = ~used & (nb == 32 ? ~0u : ((1u << nb) - 1u));
+                                    if (freeb == 0) continue;
+                                    const uint32_t bit = freeb & (0u - freeb);
+                                    const uint32_t old = __hip_atomic_fetch_or(a.slot_bits + w, bit, __ATOMIC_ACQUIRE,
+                                                                               __HIP_MEMORY_SCOPE_AGENT);
+                                    if (!(old & bit)) got = 32 * w + __builtin_ctz(bit);
+                                }
+                                sc[6] = got;
+                                sc[7] = ms.cx;
+                                sc[8] = ms.cy;
+                                sc[9] = ms.hxn;
+                                sc[10] = ms.hyn;
+                                sc[11] = ms.hon;
+                            }
+                            __syncthreads();
+                            slot = sc[6];
+                            if (slot < 0) {
+                                flags = ANN_ERESOURCE;
+                            } else {
+                                const MSeqMem g = mseq_carve(a.gheap + int64_t(slot) * slot_bytes, a.gms_cap, K);
+                                const MSeqMem l = msc.m;
+                                for (int i = lane; i < sc[7]; i += WAVE) g.mx[i] = l.mx[i];
+                                for (int i = lane; i < sc[8]; i += WAVE) g.my[i] = l.my[i];
+                                for (int i = lane; i < sc[9]; i += WAVE) {
+                                    g.hxk[i] = l.hxk[i];
+                                    g.hxr[i] = l.hxr[i];
+                                }
+                                for (int i = lane; i < sc[10]; i += WAVE) {
+                                    g.hyk[i] = l.hyk[i];
+                                    g.hyr[i] = l.hyr[i];
+                                }
+                                for (int i = lane; i < sc[11]; i += WAVE) {
+                                    g.hok[i] = l.hok[i];
+                                    g.hor[i] = l.hor[i];
+                                }
+                                msc.m = g;
+                            }
+                            __syncthreads();
+                        }
+                    }
                 }
                 bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
             }
@@ -609,8 +867,32 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                 ev = white && r < take;
                 id = ac_id;
                 dist = ac_d;
+            } else if ((ids_mask >> ring_h) & 1u) {
+                // ---- a bridge whose short list was fetched ahead (Sec. 4.1 bridge graph)
+                const int e = ring_h;
+                const int len = int(ring_len[e]);
+                ++ring_h;
+                bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
+                ++st_bpop;
+                st_bids += len;
+                id = lane < len ? pre_id[e * PRE_LIST + lane] : ID_EMPTY;
+                bool white = false;
+                if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
+                const uint64_t wm = __ballot(white);
+                take = min(int(__popcll(wm)), T - t);
+                r = lanes_below(wm);
+                ev = white && r < take;
+                if ((dist_mask >> e) & 1u) {
+                    dist = pre_d[e * PRE_LIST + lane];  // measured ahead: white then, so not visited then
+                } else {
+                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
+                    const bool miss = ev && slot < 0;
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
+                    st_rows += __popcll(__ballot(miss));
+                    dist = slot >= 0 ? DV[slot] : gdist;
+                }
             } else {
-                // ---- a bridge: its list of references (Sec. 4.1 bridge graph)
+                // ---- a bridge with a long list: walked from global memory
                 const int64_t base = ring_off[ring_h];
                 const int len = int(ring_len[ring_h]);
                 ++ring_h;
@@ -651,8 +933,16 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             }
         }
 
+        if (!RERUN && slot >= 0) {
+            // give the slot back once this wave's last write to it is done
+            if (lane == 0) {
+                __threadfence();
+                __hip_atomic_fetch_and(a.slot_bits + slot / 32, ~(1u << (slot % 32)), __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         if (!RERUN && flags) {
-            // the LDS heap overflowed: the re-run kernel redoes this query
+            // no room for the multi-sequence state: the re-run kernel redoes this query
             if (lane == 0) a.ovf_list[atomicAdd(a.ovf_count, 1u)] = uint32_t(qi);
             __syncthreads();
             continue;
@@ -724,9 +1014,9 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             s[ANN_STAT_FLAGS] = flags;
             s[ANN_STAT_ROWS] = st_rows;
             s[ANN_STAT_LOOKAHEADS] = st_spec;
-            s[ANN_STAT_LOOKAHEADS + 1] = 0;
-            s[ANN_STAT_LOOKAHEADS + 2] = 0;
-            s[ANN_STAT_LOOKAHEADS + 3] = 0;
+            s[ANN_STAT_RERUN] = RERUN ? 1 : 0;
+            s[ANN_STAT_MOVED] = slot >= 0 ? 1 : 0;
+            s[ANN_STAT_MOVED + 1] = 0;
         }
         __syncthreads();
     }
@@ -802,16 +1092,17 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
         return o;
     };
     a.o_q = take(align_up(qbytes, 16), 16);
-    a.o_tab = take(PK * 4, 8);
     a.o_sv = take(PK * 4, 8);
     a.o_perm = take(PK, 8);
-    a.o_hk = with_heap ? take(a.heap_cap * 8, 8) : 0;
-    a.o_hr = with_heap ? take(a.heap_cap * 4, 8) : 0;
+    a.o_ms = with_heap ? take(mseq_bytes(a.ms_cap, a.K), 16) : 0;
     a.o_rk = take(GEN_BATCH * 8, 8);
     a.o_ro = take(GEN_BATCH * 4, 8);
     a.o_rl = take(GEN_BATCH * 4, 8);
-    a.o_sk = take(GEN_BATCH * 8, 8);
-    a.o_hash = take(int(a.hash_buckets) * 16, 16);
+    a.o_sk = a.o_rk;  // a batch is staged where it is compacted into the ring
+    a.o_pid = a.prefetch ? take(GEN_BATCH * PRE_LIST * 4, 16) : 0;
+    a.o_pd = a.prefetch ? take(GEN_BATCH * PRE_LIST * 4, 16) : 0;
+    // the visited set also holds the raw distance tables before the search
+    a.o_hash = take(std::max(int(a.hash_buckets) * 16, PK * 4), 16);
     a.o_dck = take(int(a.dc_buckets) * 16, 16);
     a.o_dcv = take(int(a.dc_buckets) * 16, 16);
     // re-rank keys (bf16) and the row list of multi-lane gathers (fp32, bf16)
@@ -861,12 +1152,19 @@ struct Plan {
     SearchArgs a, a2;
     int lds1 = 0, lds2 = 0, rcap = 0;
     bool bf16 = false, is_f32 = false;
-    int grid2 = 64;
+    int grid2 = 128;
     int64_t gcap = 0;
-    size_t ws_bytes = 0;
+    size_t slot_bytes = 0, fixed_bytes = 0;
+    size_t ws_bytes = 0;  // with kMaxSlots slots
 };
 
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
+
+// Global slots for multi-sequence state that outgrows LDS.  A workspace
+// smaller than the full size gets fewer slots (at least one); the bitmap of
+// slots in use lives in the counter block.
+constexpr int kMaxSlots = 256;
+constexpr int kSlotBitsWord = 8;  // first word of the bitmap in the counter block
 
 static int make_plan(const SearchLaunch& s, Plan& pl) {
     const ann_index* idx = s.idx;
@@ -912,8 +1210,14 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.dc_buckets = 128;  // distance cache: 512 slots, cleared when half full
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
-    // LDS frontier of the multi-sequence; larger ones go to the re-run kernel
-    a.heap_cap = int(std::min<int64_t>(idx->nb, 192));
+    // multi-sequence capacity in LDS (materialised side elements and outer
+    // frontier), by budget; a query that outgrows it moves its state to a
+    // global slot and carries on.  Up to T = 2048 the kNN graph does almost
+    // all the work (one bridge per query on the 1M workload); beyond it
+    // bridges take over and their lists are fetched ahead.
+    const int64_t side = int64_t(idx->K) * idx->K;
+    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 64)) : int(std::min<int64_t>(side, 1024));
+    a.prefetch = s.Tmax > 2048 ? 1 : 0;
 
     const int qbytes = pl.is_f32 ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
@@ -924,10 +1228,12 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
     pl.lds2 = layout(pl.a2, qbytes, PK, pl.rcap, false, pl.bf16, lpr);
 
-    // workspace: counters | overflow list | order buckets | order | re-run heaps
-    pl.gcap = std::min<int64_t>(idx->nb, std::max<int64_t>(4096, 8 * int64_t(s.Tmax) + 1024));
-    pl.ws_bytes = 256 + round16(size_t(s.nq) * 4) + 256 + round16(size_t(s.nq) * 4) +
-                  size_t(pl.grid2) * size_t(pl.gcap) * 12;
+    // workspace: counters and slot bitmap | overflow list | order buckets |
+    // order | global multi-sequence slots (a side holds at most K^2 elements)
+    pl.gcap = std::min<int64_t>(int64_t(idx->K) * idx->K, 8192);
+    pl.slot_bytes = size_t(mseq_slot_bytes(int(pl.gcap), idx->K));
+    pl.fixed_bytes = (256 + round16(size_t(s.nq) * 4) + 256 + round16(size_t(s.nq) * 4) + 63) & ~size_t(63);
+    pl.ws_bytes = pl.fixed_bytes + size_t(kMaxSlots) * pl.slot_bytes;
     return ANN_OK;
 }
 
@@ -958,13 +1264,20 @@ int launch_search(const SearchLaunch& s) {
 
     uint8_t* w = static_cast<uint8_t*>(s.workspace);
     const bool own = w == nullptr;
+    int nslots = kMaxSlots;
     if (own) {
         ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), pl.ws_bytes, s.stream));
     } else {
-        ANN_REQUIRE(s.workspace_bytes >= int64_t(pl.ws_bytes), "search: workspace too small");
+        ANN_REQUIRE(s.workspace_bytes >= int64_t(pl.fixed_bytes + pl.slot_bytes),
+                    "search: workspace too small (" + std::to_string(s.workspace_bytes) + " bytes, at least " +
+                        std::to_string(pl.fixed_bytes + pl.slot_bytes) + " needed)");
         ANN_REQUIRE((reinterpret_cast<uintptr_t>(w) & 15) == 0, "search: workspace must be 16-byte aligned");
+        nslots = int(std::min<int64_t>(kMaxSlots, (s.workspace_bytes - int64_t(pl.fixed_bytes)) /
+                                                      int64_t(pl.slot_bytes)));
     }
-    uint32_t* counters = reinterpret_cast<uint32_t*>(w);  // [0] overflow count, [1] work counter
+    pl.grid2 = std::min(pl.grid2, nslots);
+    // [0] overflow count, [1] work counter, [8, 16) bitmap of global slots in use
+    uint32_t* counters = reinterpret_cast<uint32_t*>(w);
     size_t o = 256;
     uint32_t* ovf_list = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
@@ -972,13 +1285,16 @@ int launch_search(const SearchLaunch& s) {
     o += 256;
     uint32_t* perm = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
+    o = (o + 63) & ~size_t(63);  // == pl.fixed_bytes
     uint8_t* gheap = w + o;
 
     a.ovf_count = a2.ovf_count = counters;
     a.ovf_list = a2.ovf_list = ovf_list;
     a.gheap = a2.gheap = gheap;
-    a.gheap_cap = a2.gheap_cap = int(pl.gcap);
-    a2.heap_cap = a.heap_cap;
+    a.gms_cap = a2.gms_cap = int(pl.gcap);
+    a.nslots = a2.nslots = nslots;
+    a.slot_bits = a2.slot_bits = counters + kSlotBitsWord;
+    a2.ms_cap = a.ms_cap;
     a.work_counter = s.persistent ? counters + 1 : nullptr;
     a2.work_counter = nullptr;
     a.perm = nullptr;

@@ -235,3 +235,66 @@ def test_f32_search_within_tolerance():
         ex = ((X[bi[i]].astype(np.float64) - Q[i].astype(np.float64)) ** 2).sum(1)
         np.testing.assert_allclose(bd[i], ex, rtol=1e-4)
         assert (np.diff(bd[i]) >= 0).all()
+
+
+# ---------------------------------------------------------------- bridge-heavy searches
+
+@pytest.mark.parametrize("n,P,K,t,b,T,k", [
+    (3000, 4, 8, 10, 5, 2000, 10),    # short lists fetched ahead with their distances
+    (2500, 3, 12, 6, 3, 2400, 20),    # P = 3: one side of two lists, one of one
+    (2000, 2, 40, 4, 2, 1900, 5),     # P = 2: both sides plain lists
+    (4000, 4, 9, 25, 0, 3900, 10),    # all kept: long lists walked from memory
+])
+def test_bridge_heavy_search_bit_exact(n, P, K, t, b, T, k):
+    rng = np.random.default_rng(n + K)
+    X = rng.integers(0, 256, size=(n, 48)).astype(np.uint8)
+    Q = rng.integers(0, 256, size=(20, 48)).astype(np.uint8)
+    # a sparse graph (R = 2) exhausts its neighbourhoods quickly; bridges take over
+    idx = _index_cls().build(X, 2, P, K, 3, 99, t, b)
+    parts = idx.export()
+    gi, gd, st = gpu_search(idx, Q, k, T, 64, stats=True)
+    assert (st[:, 2] > 40).all()            # many bridges expanded per query
+    assert (st[:, 6] == 0).all()
+    assert_search_equal(idx, parts, X, Q, k, T, 64)
+
+
+def _overflow_case():
+    rng = np.random.default_rng(77)
+    n = 2000
+    X = rng.integers(0, 256, size=(n, 32)).astype(np.uint8)
+    Q = rng.integers(0, 256, size=(12, 32)).astype(np.uint8)
+    idx = _index_cls().build(X, 1, 4, 16, 2, 5, 3, 1)   # 65,536 bridges, lists of one
+    return X, Q, idx, idx.export()
+
+
+def test_multisequence_overflow_moves_to_a_global_slot_exactly():
+    """At T <= 2048 the LDS enumeration holds 64 elements per side; a query that
+    needs more carries on with its state in a global slot."""
+    X, Q, idx, parts = _overflow_case()
+    gi, gd, st = gpu_search(idx, Q, 10, 1800, 64, stats=True)
+    assert (st[:, 10] == 1).any()           # some queries outgrew the LDS capacity
+    assert (st[:, 9] == 0).all()            # ... and found a free slot
+    assert (st[:, 6] == 0).all()
+    assert_search_equal(idx, parts, X, Q, 10, 1800, 64)
+
+
+def test_multisequence_overflow_without_a_free_slot_is_rerun_exactly():
+    """A workspace with room for one global slot: queries that find it taken
+    are searched again by the second kernel, with the same results."""
+    X, Q, idx, parts = _overflow_case()
+    nq, k, T = len(Q), 10, 1800
+    # the full workspace is a few hundred bytes of per-query lists plus 256
+    # slots of several KB: 1/128 of it holds the lists and one slot, not two
+    small = torch.empty(idx.workspace_bytes(nq, k, T) // 128, dtype=torch.uint8, device="cuda")
+    qd = torch.from_numpy(Q).cuda()
+    st = torch.empty((nq, 12), dtype=torch.int32, device="cuda")
+    ids, dd = idx.search_device(qd, k, T, stats=st, workspace=small)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert ((st[:, 9] == 1) | (st[:, 10] == 1)).sum() >= 2
+    assert (st[:, 9] == 1).any()            # the slot was in use: re-run
+    assert (st[:, 6] == 0).all()
+    oi, od = oracle.search(X, parts["codebooks"], parts["graph"], parts["bridge_off"], parts["bridge_ids"], Q,
+                           k, T, 64)
+    np.testing.assert_array_equal(ids.cpu().numpy(), oi)
+    np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
