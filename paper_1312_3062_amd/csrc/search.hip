@@ -391,29 +391,46 @@ struct MSeqMem {
     uint32_t* hyr;
     uint64_t* hok;  // outer heap: keys sum << 32 | n + lid, positions i << 16 | j
     uint32_t* hor;
-    int cap;        // capacity of mx, my and hok
+    int cap;        // capacity of mx and my
+    int ocap;       // of the outer heap
 };
 
-__host__ __device__ inline int mseq_bytes(int cap, int K) {
-    const int ocap = cap + K + 1;
-    return cap * 8 * 2 + ocap * 12 + (K + 1) * 12 * 2 + 64;
+// Capacities.  A frontier holds at most one entry per started row, and a row
+// is started only once the element heading it is known: the outer frontier
+// never exceeds the X elements materialised (K when X is one list), and an
+// inner frontier never exceeds one more than the elements it has produced.
+struct MSeqCaps {
+    int cap, ocap, icap;
+};
+__host__ __device__ inline MSeqCaps mseq_caps(int cap, int K, int P) {
+    MSeqCaps c;
+    c.cap = cap;
+    c.ocap = P >= 3 ? cap + 2 : K + 1;
+    c.icap = cap + 2 < K + 1 ? cap + 2 : K + 1;
+    return c;
+}
+
+__host__ __device__ inline int mseq_bytes(int cap, int K, int P) {
+    const MSeqCaps c = mseq_caps(cap, K, P);
+    return c.cap * 8 * 2 + c.ocap * 12 + c.icap * 12 * 2 + 64;
 }
 
 // a global slot: mseq_bytes rounded up so that every slot starts 64-byte aligned
-__host__ __device__ inline int mseq_slot_bytes(int cap, int K) { return (mseq_bytes(cap, K) + 63) & ~63; }
+__host__ __device__ inline int mseq_slot_bytes(int cap, int K, int P) { return (mseq_bytes(cap, K, P) + 63) & ~63; }
 
-__device__ inline MSeqMem mseq_carve(uint8_t* base, int cap, int K) {
+__device__ inline MSeqMem mseq_carve(uint8_t* base, int cap, int K, int P) {
+    const MSeqCaps c = mseq_caps(cap, K, P);
     MSeqMem m;
-    const int ocap = cap + K + 1;
     m.mx = reinterpret_cast<uint64_t*>(base);
-    m.my = m.mx + cap;
-    m.hok = m.my + cap;
-    m.hxk = m.hok + ocap;
-    m.hyk = m.hxk + (K + 1);
-    m.hor = reinterpret_cast<uint32_t*>(m.hyk + (K + 1));
-    m.hxr = m.hor + ocap;
-    m.hyr = m.hxr + (K + 1);
-    m.cap = cap;
+    m.my = m.mx + c.cap;
+    m.hok = m.my + c.cap;
+    m.hxk = m.hok + c.ocap;
+    m.hyk = m.hxk + c.icap;
+    m.hor = reinterpret_cast<uint32_t*>(m.hyk + c.icap);
+    m.hxr = m.hor + c.ocap;
+    m.hyr = m.hxr + c.icap;
+    m.cap = c.cap;
+    m.ocap = c.ocap;
     return m;
 }
 
@@ -503,7 +520,7 @@ struct PairMSeq {
     __device__ void outer_push(const MSeqConf& c, uint32_t i, uint32_t j) {
         uint32_t sx, lx, sy, ly;
         if (!elem(c, true, i, sx, lx) || !elem(c, false, j, sy, ly)) return;
-        if (hon >= c.m.cap + c.K + 1) {
+        if (hon >= c.m.ocap) {
             of = true;
             return;
         }
@@ -517,7 +534,7 @@ struct PairMSeq {
     __device__ bool tight(const MSeqConf& c) const {
         const bool x = c.nx == 2 && cx >= c.m.cap && uint32_t(cx) < c.sizeX;
         const bool y = c.ny == 2 && cy >= c.m.cap && uint32_t(cy) < c.sizeY;
-        return x || y || hon + 2 > c.m.cap + c.K + 1;
+        return x || y || hon + 2 > c.m.ocap;
     }
     __device__ void init(const MSeqConf& c) {
         cx = cy = hxn = hyn = hon = maxf = 0;
@@ -560,12 +577,12 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     uint32_t* gd = reinterpret_cast<uint32_t*>(lds + a.o_gd);
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
 
-    const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, a.K);
+    const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, a.K, a.P);
     MSeqMem msm;
     if constexpr (RERUN)
-        msm = mseq_carve(a.gheap + int64_t(blockIdx.x) * slot_bytes, a.gms_cap, a.K);
+        msm = mseq_carve(a.gheap + int64_t(blockIdx.x) * slot_bytes, a.gms_cap, a.K, a.P);
     else
-        msm = mseq_carve(lds + a.o_ms, a.ms_cap, a.K);
+        msm = mseq_carve(lds + a.o_ms, a.ms_cap, a.K, a.P);
 
     const int lane = lane_id();
     const int64_t n = a.n;
@@ -774,7 +791,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                             if (slot < 0) {
                                 flags = ANN_ERESOURCE;
                             } else {
-                                const MSeqMem g = mseq_carve(a.gheap + int64_t(slot) * slot_bytes, a.gms_cap, K);
+                                const MSeqMem g = mseq_carve(a.gheap + int64_t(slot) * slot_bytes, a.gms_cap, K, P);
                                 const MSeqMem l = msc.m;
                                 for (int i = lane; i < sc[7]; i += WAVE) g.mx[i] = l.mx[i];
                                 for (int i = lane; i < sc[8]; i += WAVE) g.my[i] = l.my[i];
@@ -1094,7 +1111,7 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
     a.o_q = take(align_up(qbytes, 16), 16);
     a.o_sv = take(PK * 4, 8);
     a.o_perm = take(PK, 8);
-    a.o_ms = with_heap ? take(mseq_bytes(a.ms_cap, a.K), 16) : 0;
+    a.o_ms = with_heap ? take(mseq_bytes(a.ms_cap, a.K, a.P), 16) : 0;
     a.o_rk = take(GEN_BATCH * 8, 8);
     a.o_ro = take(GEN_BATCH * 4, 8);
     a.o_rl = take(GEN_BATCH * 4, 8);
@@ -1155,16 +1172,19 @@ struct Plan {
     int grid2 = 128;
     int64_t gcap = 0;
     size_t slot_bytes = 0, fixed_bytes = 0;
-    size_t ws_bytes = 0;  // with kMaxSlots slots
+    int max_slots = 0;
+    size_t ws_bytes = 0;  // with max_slots slots
 };
 
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 
-// Global slots for multi-sequence state that outgrows LDS.  A workspace
-// smaller than the full size gets fewer slots (at least one); the bitmap of
-// slots in use lives in the counter block.
-constexpr int kMaxSlots = 256;
-constexpr int kSlotBitsWord = 8;  // first word of the bitmap in the counter block
+// Global slots for multi-sequence state that outgrows LDS.  Up to T = 2048
+// few queries need one and 256 slots serve them; above it most queries move,
+// so there is a slot for every workgroup that can be resident.  At most
+// 512 MiB of slots.  A workspace smaller than the full size gets fewer slots
+// (at least one).
+constexpr int kSmallBudgetSlots = 256;
+constexpr size_t kMaxSlotBytes = size_t(512) << 20;
 
 static int make_plan(const SearchLaunch& s, Plan& pl) {
     const ann_index* idx = s.idx;
@@ -1205,9 +1225,9 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.trace = s.d_trace;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates); buckets for a final load of about 0.75
-    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 4 / 3 / 4 + 1));
-    a.dc_buckets = 128;  // distance cache: 512 slots, cleared when half full
+    // than it evaluates); buckets for a final load of about 0.8
+    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
+    a.dc_buckets = 96;  // distance cache: 384 slots, cleared when half full
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
     // multi-sequence capacity in LDS (materialised side elements and outer
@@ -1216,7 +1236,7 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // all the work (one bridge per query on the 1M workload); beyond it
     // bridges take over and their lists are fetched ahead.
     const int64_t side = int64_t(idx->K) * idx->K;
-    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 64)) : int(std::min<int64_t>(side, 1024));
+    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 16)) : int(std::min<int64_t>(side, 256));
     a.prefetch = s.Tmax > 2048 ? 1 : 0;
 
     const int qbytes = pl.is_f32 ? idx->d * 4 : idx->d;
@@ -1228,12 +1248,20 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
     pl.lds2 = layout(pl.a2, qbytes, PK, pl.rcap, false, pl.bf16, lpr);
 
-    // workspace: counters and slot bitmap | overflow list | order buckets |
+    // workspace: counters | slot bitmap | overflow list | order buckets |
     // order | global multi-sequence slots (a side holds at most K^2 elements)
     pl.gcap = std::min<int64_t>(int64_t(idx->K) * idx->K, 8192);
-    pl.slot_bytes = size_t(mseq_slot_bytes(int(pl.gcap), idx->K));
-    pl.fixed_bytes = (256 + round16(size_t(s.nq) * 4) + 256 + round16(size_t(s.nq) * 4) + 63) & ~size_t(63);
-    pl.ws_bytes = pl.fixed_bytes + size_t(kMaxSlots) * pl.slot_bytes;
+    pl.slot_bytes = size_t(mseq_slot_bytes(int(pl.gcap), idx->K, idx->P));
+    int cus = 0, lds_cu = 0;
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, idx->device));
+    const int64_t resident = int64_t(cus) * std::max(1, std::min(32, lds_cu / std::max(1, pl.lds1)));
+    int64_t slots = s.Tmax > 2048 ? resident : kSmallBudgetSlots;
+    slots = std::min<int64_t>(slots, int64_t(kMaxSlotBytes / pl.slot_bytes));
+    pl.max_slots = int(std::max<int64_t>(1, std::min<int64_t>(slots, s.nq)));
+    pl.fixed_bytes = (256 + round16(size_t(ceil_div(pl.max_slots, 32)) * 4) + round16(size_t(s.nq) * 4) + 256 +
+                      round16(size_t(s.nq) * 4) + 63) & ~size_t(63);
+    pl.ws_bytes = pl.fixed_bytes + size_t(pl.max_slots) * pl.slot_bytes;
     return ANN_OK;
 }
 
@@ -1264,7 +1292,7 @@ int launch_search(const SearchLaunch& s) {
 
     uint8_t* w = static_cast<uint8_t*>(s.workspace);
     const bool own = w == nullptr;
-    int nslots = kMaxSlots;
+    int nslots = pl.max_slots;
     if (own) {
         ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), pl.ws_bytes, s.stream));
     } else {
@@ -1272,13 +1300,16 @@ int launch_search(const SearchLaunch& s) {
                     "search: workspace too small (" + std::to_string(s.workspace_bytes) + " bytes, at least " +
                         std::to_string(pl.fixed_bytes + pl.slot_bytes) + " needed)");
         ANN_REQUIRE((reinterpret_cast<uintptr_t>(w) & 15) == 0, "search: workspace must be 16-byte aligned");
-        nslots = int(std::min<int64_t>(kMaxSlots, (s.workspace_bytes - int64_t(pl.fixed_bytes)) /
-                                                      int64_t(pl.slot_bytes)));
+        nslots = int(std::min<int64_t>(pl.max_slots, (s.workspace_bytes - int64_t(pl.fixed_bytes)) /
+                                                         int64_t(pl.slot_bytes)));
     }
     pl.grid2 = std::min(pl.grid2, nslots);
-    // [0] overflow count, [1] work counter, [8, 16) bitmap of global slots in use
+    // [0] overflow count, [1] work counter
     uint32_t* counters = reinterpret_cast<uint32_t*>(w);
     size_t o = 256;
+    const int bit_words = ceil_div(pl.max_slots, 32);
+    uint32_t* slot_bits = reinterpret_cast<uint32_t*>(w + o);  // global slots in use
+    o += round16(size_t(bit_words) * 4);
     uint32_t* ovf_list = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
     uint32_t* buckets = reinterpret_cast<uint32_t*>(w + o);  // 32 starts + 32 cursors
@@ -1293,13 +1324,14 @@ int launch_search(const SearchLaunch& s) {
     a.gheap = a2.gheap = gheap;
     a.gms_cap = a2.gms_cap = int(pl.gcap);
     a.nslots = a2.nslots = nslots;
-    a.slot_bits = a2.slot_bits = counters + kSlotBitsWord;
+    a.slot_bits = a2.slot_bits = slot_bits;
     a2.ms_cap = a.ms_cap;
     a.work_counter = s.persistent ? counters + 1 : nullptr;
     a2.work_counter = nullptr;
     a.perm = nullptr;
     // counters and order buckets are cleared by a kernel (no memset nodes in captured graphs)
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, counters, 64);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, slot_bits, bit_words);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, buckets, 64);
     if (s.persistent && s.order && s.d_T) {
         const unsigned gb = unsigned(ceil_div(s.nq, 256));

@@ -283,9 +283,10 @@ def test_multisequence_overflow_without_a_free_slot_is_rerun_exactly():
     are searched again by the second kernel, with the same results."""
     X, Q, idx, parts = _overflow_case()
     nq, k, T = len(Q), 10, 1800
-    # the full workspace is a few hundred bytes of per-query lists plus 256
-    # slots of several KB: 1/128 of it holds the lists and one slot, not two
-    small = torch.empty(idx.workspace_bytes(nq, k, T) // 128, dtype=torch.uint8, device="cuda")
+    # at this budget the full workspace has one slot of several KB per query
+    # (12 <= 256) and a few hundred bytes of lists: 3/(2 nq) of it holds the
+    # lists and one slot, not two
+    small = torch.empty(idx.workspace_bytes(nq, k, T) * 3 // (2 * nq), dtype=torch.uint8, device="cuda")
     qd = torch.from_numpy(Q).cuda()
     st = torch.empty((nq, 12), dtype=torch.int32, device="cuda")
     ids, dd = idx.search_device(qd, k, T, stats=st, workspace=small)
