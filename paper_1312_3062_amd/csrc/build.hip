@@ -45,108 +45,128 @@ namespace {
 constexpr int KM_THREADS = 256;
 
 // ----------------------------------------------------------------------
-// k-means assignment + per-workgroup partial sums.  One thread per point,
-// all subspaces; centroids of every subspace cached in LDS.
-//   u8: nearest by |x|^2 - 2 x.c + |c|^2 (exact ints), ties to smaller j;
-//       member sums exact in uint64.
-//   f32: nearest by fp32 sum (x - c)^2; sums in int64 fixed point
-//       (x * 2^scale_log2 rounded), so the reduction order does not matter.
+// k-means (Sec. 3.2 product quantisation, per subspace), one subspace at a
+// time.
+//   assign: one thread per point; the subspace's codewords stream through
+//     LDS in chunks, every thread reading the same codeword at once.
+//     u8: nearest by |c|^2 - 2 x.c (|x|^2 is common), exact ints;
+//     f32: nearest by the fp32 sum of (x - c)^2.  Ties go to the smaller j.
+//   accum: member sums over a slice of at most 64 dimensions; lanes cover
+//     consecutive dimensions of one point (coalesced rows, distinct LDS
+//     addresses), per-workgroup sums in LDS, then global atomics.  u8 sums
+//     are exact integers; f32 values enter as int64 fixed point
+//     (x * 2^scale rounded), so the order of the additions does not matter.
 // ----------------------------------------------------------------------
-// per-workgroup member sums: 256 bytes fit uint32; f32 fixed point needs 64 bits
 template <bool FLOAT>
 using lsum_t = typename std::conditional<FLOAT, unsigned long long, unsigned int>::type;
 
+constexpr int KM_CHUNK_BYTES = 32768;  // codewords staged in LDS per pass
+constexpr int KM_SLICE = 64;           // dimensions summed by one workgroup
+constexpr int KM_POINTS = 2048;        // points per accumulation workgroup
+
 template <bool FLOAT>
-__host__ __device__ inline int kmeans_lds_bytes(int P, int K, int ds) {
-    const int PKd = P * K * ds;
-    return ((PKd * (FLOAT ? 4 : 1) + 15) & ~15) + ((P * K * 4 + 15) & ~15) +
-           ((PKd * int(sizeof(lsum_t<FLOAT>)) + 15) & ~15) + P * K * 4;
+__global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int K,
+                                                              const void* cb_p, int kc, int32_t* assign) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const int esz = FLOAT ? 4 : 1;
+    uint8_t* c_l = lds;                                                  // kc codewords
+    uint32_t* cnorm = reinterpret_cast<uint32_t*>(lds + ((kc * ds * esz + 15) & ~15));  // u8: |c|^2
+    const int64_t i = int64_t(blockIdx.x) * KM_THREADS + threadIdx.x;
+    const bool live = i < n;
+    int best = 0;
+    uint32_t bd = 0;
+    for (int j0 = 0; j0 < K; j0 += kc) {
+        const int m = min(kc, K - j0);
+        __syncthreads();
+        const int words = (m * ds * esz) / 4;
+        const uint8_t* src = static_cast<const uint8_t*>(cb_p) + int64_t(j0) * ds * esz;
+        for (int w = threadIdx.x; w < words; w += KM_THREADS)
+            reinterpret_cast<uint32_t*>(c_l)[w] = reinterpret_cast<const uint32_t*>(src)[w];
+        for (int w = words * 4 + threadIdx.x; w < m * ds * esz; w += KM_THREADS) c_l[w] = src[w];
+        __syncthreads();
+        if constexpr (!FLOAT) {
+            for (int e = threadIdx.x; e < m; e += KM_THREADS) {
+                uint32_t s2 = 0;
+                for (int q = 0; q < ds; ++q) s2 += uint32_t(c_l[e * ds + q]) * c_l[e * ds + q];
+                cnorm[e] = s2;
+            }
+            __syncthreads();
+        }
+        if (!live) continue;
+        for (int jj = 0; jj < m; ++jj) {
+            const int j = j0 + jj;
+            uint32_t dist;
+            if constexpr (!FLOAT) {
+                const uint8_t* x = X + i * d + int64_t(p) * ds;
+                const uint8_t* c = c_l + jj * ds;
+                uint32_t dot = 0;
+                int e = 0;
+                if ((ds & 3) == 0) {
+                    for (; e < ds; e += 4) {
+                        uint32_t xw, cw;
+                        __builtin_memcpy(&xw, x + e, 4);
+                        __builtin_memcpy(&cw, c + e, 4);
+                        dot = __builtin_amdgcn_udot4(xw, cw, dot, false);
+                    }
+                }
+                for (; e < ds; ++e) dot += uint32_t(x[e]) * c[e];
+                dist = cnorm[jj] - 2u * dot + 0x80000000u;  // order-preserving bias (value may be negative)
+            } else {
+                const float* x = reinterpret_cast<const float*>(X) + i * d + int64_t(p) * ds;
+                const float* c = reinterpret_cast<const float*>(c_l) + jj * ds;
+                float acc = 0.f;
+                for (int e = 0; e < ds; ++e) {
+                    const float t = x[e] - c[e];
+                    acc = fmaf(t, t, acc);
+                }
+                dist = __float_as_uint(acc);
+            }
+            if (j == 0 || dist < bd) {
+                bd = dist;
+                best = j;
+            }
+        }
+    }
+    if (live) assign[i] = best;
 }
 
 template <bool FLOAT>
-__global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, int64_t n, int d, int P, int K,
-                                                               const void* cb, uint64_t* sums, uint32_t* counts,
-                                                               int32_t* assign, float fx_scale) {
+__global__ void __launch_bounds__(KM_THREADS) k_kmeans_accum(const uint8_t* X, int64_t n, int d, int ds, int p, int K,
+                                                             const int32_t* assign, float fx_scale, uint64_t* sums_p,
+                                                             uint32_t* counts_p) {
     extern __shared__ __align__(16) uint8_t lds[];
-    const int ds = d / P;
-    const int esz = FLOAT ? 4 : 1;
-    const int PKd0 = P * K * ds;
-    uint8_t* c_l = lds;                                                   // P*K*ds elements
-    const int cbytes = (PKd0 * esz + 15) & ~15;
-    uint32_t* cnorm = reinterpret_cast<uint32_t*>(lds + cbytes);        // P*K (u8)
-    lsum_t<FLOAT>* lsum = reinterpret_cast<lsum_t<FLOAT>*>(lds + cbytes + ((P * K * 4 + 15) & ~15));  // P*K*ds
-    uint32_t* lcnt = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(lsum) +
-                                                 ((PKd0 * int(sizeof(lsum_t<FLOAT>)) + 15) & ~15));  // P*K
-    const int PKd = P * K * ds;
-    for (int i = threadIdx.x; i < PKd * esz / 4; i += KM_THREADS)
-        reinterpret_cast<uint32_t*>(c_l)[i] = static_cast<const uint32_t*>(cb)[i];
-    for (int i = threadIdx.x; i < PKd; i += KM_THREADS) lsum[i] = 0;
-    for (int i = threadIdx.x; i < P * K; i += KM_THREADS) lcnt[i] = 0;
+    const int e0 = blockIdx.y * KM_SLICE;
+    const int sw = min(KM_SLICE, ds - e0);                 // dimensions in this slice
+    lsum_t<FLOAT>* lsum = reinterpret_cast<lsum_t<FLOAT>*>(lds);  // K x sw
+    uint32_t* lcnt = reinterpret_cast<uint32_t*>(lds + ((K * sw * int(sizeof(lsum_t<FLOAT>)) + 15) & ~15));
+    for (int w = threadIdx.x; w < K * sw; w += KM_THREADS) lsum[w] = 0;
+    for (int w = threadIdx.x; w < K; w += KM_THREADS) lcnt[w] = 0;
     __syncthreads();
-    if constexpr (!FLOAT) {
-        for (int e = threadIdx.x; e < P * K; e += KM_THREADS) {
-            uint32_t s = 0;
-            for (int i = 0; i < ds; ++i) s += uint32_t(c_l[e * ds + i]) * c_l[e * ds + i];
-            cnorm[e] = s;
-        }
-        __syncthreads();
-    }
-    const int64_t i = int64_t(blockIdx.x) * KM_THREADS + threadIdx.x;
-    if (i < n) {
-        for (int p = 0; p < P; ++p) {
-            int best = 0;
-            uint32_t bd = 0;
-            for (int j = 0; j < K; ++j) {
-                uint32_t dist;
-                if constexpr (!FLOAT) {
-                    const uint8_t* x = X + i * d + p * ds;
-                    const uint8_t* c = c_l + (p * K + j) * ds;
-                    uint32_t dot = 0;
-                    int e = 0;
-                    if ((ds & 3) == 0) {
-                        for (; e < ds; e += 4) {
-                            uint32_t xw, cw;
-                            __builtin_memcpy(&xw, x + e, 4);
-                            __builtin_memcpy(&cw, c + e, 4);
-                            dot = __builtin_amdgcn_udot4(xw, cw, dot, false);
-                        }
-                    }
-                    for (; e < ds; ++e) dot += uint32_t(x[e]) * c[e];
-                    dist = cnorm[p * K + j] - 2u * dot;  // |x|^2 is common to all j
-                    dist += 0x80000000u;                  // order-preserving bias (value may be negative)
-                } else {
-                    const float* x = reinterpret_cast<const float*>(X) + i * d + p * ds;
-                    const float* c = reinterpret_cast<const float*>(c_l) + (p * K + j) * ds;
-                    float acc = 0.f;
-                    for (int e = 0; e < ds; ++e) {
-                        const float t = x[e] - c[e];
-                        acc = fmaf(t, t, acc);
-                    }
-                    dist = __float_as_uint(acc);
-                }
-                if (j == 0 || dist < bd) {
-                    bd = dist;
-                    best = j;
-                }
-            }
-            if (assign) assign[i * P + p] = best;
-            atomicAdd(&lcnt[p * K + best], 1u);
-            for (int e = 0; e < ds; ++e) {
-                lsum_t<FLOAT> v;
-                if constexpr (!FLOAT)
-                    v = X[i * d + p * ds + e];
-                else
-                    v = static_cast<unsigned long long>(
-                        __float2ll_rn(reinterpret_cast<const float*>(X)[i * d + p * ds + e] * fx_scale));
-                atomicAdd(&lsum[(p * K + best) * ds + e], v);
-            }
+    const int per = KM_THREADS / sw;  // points per pass (sw divides neither? then some lanes idle)
+    const int e = threadIdx.x % sw, r = threadIdx.x / sw;
+    const int64_t p0 = int64_t(blockIdx.x) * KM_POINTS;
+    const int64_t p1 = min<int64_t>(n, p0 + KM_POINTS);
+    if (r < per) {
+        for (int64_t i = p0 + r; i < p1; i += per) {
+            const int a = assign[i];
+            lsum_t<FLOAT> v;
+            if constexpr (!FLOAT)
+                v = X[i * d + int64_t(p) * ds + e0 + e];
+            else
+                v = static_cast<unsigned long long>(
+                    __float2ll_rn(reinterpret_cast<const float*>(X)[i * d + int64_t(p) * ds + e0 + e] * fx_scale));
+            atomicAdd(&lsum[a * sw + e], v);
+            if (blockIdx.y == 0 && e == 0) atomicAdd(&lcnt[a], 1u);
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < PKd; e += KM_THREADS)
-        if (lsum[e]) atomicAdd(reinterpret_cast<unsigned long long*>(&sums[e]), static_cast<unsigned long long>(lsum[e]));
-    for (int e = threadIdx.x; e < P * K; e += KM_THREADS)
-        if (lcnt[e]) atomicAdd(&counts[e], lcnt[e]);
+    for (int w = threadIdx.x; w < K * sw; w += KM_THREADS)
+        if (lsum[w])
+            atomicAdd(reinterpret_cast<unsigned long long*>(&sums_p[(w / sw) * ds + e0 + w % sw]),
+                      static_cast<unsigned long long>(lsum[w]));
+    if (blockIdx.y == 0)
+        for (int w = threadIdx.x; w < K; w += KM_THREADS)
+            if (lcnt[w]) atomicAdd(&counts_p[w], lcnt[w]);
 }
 
 // update: member mean, u8 rounded half up in exact integers; empty keeps
@@ -345,22 +365,41 @@ int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
     // f32 sums in fixed point x * 2^fx_log2 (the caller bounds n * max|x| * 2^fx_log2 by 2^62)
     const float fx = f ? ldexpf(1.f, fx_log2) : 1.f;
     const float inv_fx = f ? ldexpf(1.f, -fx_log2) : 1.f;
-    const int lds = f ? kmeans_lds_bytes<true>(P, K, ds) : kmeans_lds_bytes<false>(P, K, ds);
+    const int esz = f ? 4 : 1;
+    const int kc = std::max(1, std::min(K, KM_CHUNK_BYTES / (ds * esz)));
+    const int lds_assign = ((kc * ds * esz + 15) & ~15) + kc * 4;
+    const int slices = int(ceil_div(ds, KM_SLICE));
+    const int sw0 = std::min(KM_SLICE, ds);
+    const int lds_accum = ((K * sw0 * (f ? 8 : 4) + 15) & ~15) + K * 4;
     int dev = 0, max_lds = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    if (lds > max_lds) return set_error(ANN_EUNSUPPORTED, "codebooks too large for the k-means kernel");
+    if (lds_accum > max_lds || lds_assign > max_lds)
+        return set_error(ANN_EUNSUPPORTED, "codebooks too large for the k-means kernels");
+    int32_t* assign = nullptr;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&assign), size_t(idx->n) * 4, s));
     const int64_t grid = ceil_div(idx->n, KM_THREADS);
+    const dim3 agrid(unsigned(ceil_div(idx->n, KM_POINTS)), unsigned(slices));
     for (int it = 0; it < iters; ++it) {
         ANN_HIP_CHECK(hipMemsetAsync(sums, 0, size_t(PKd) * 8, s));
         ANN_HIP_CHECK(hipMemsetAsync(counts, 0, size_t(P * K) * 4, s));
-        if (f)
-            hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds, s, idx->X, idx->n,
-                               idx->d, P, K, idx->codebooks, sums, counts, nullptr, fx);
-        else
-            hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds, s, idx->X,
-                               idx->n, idx->d, P, K, idx->codebooks, sums, counts, nullptr, fx);
-        ANN_HIP_CHECK(hipGetLastError());
+        for (int p = 0; p < P; ++p) {
+            const uint8_t* cb_p = static_cast<const uint8_t*>(idx->codebooks) + int64_t(p) * K * ds * esz;
+            uint64_t* sums_p = sums + int64_t(p) * K * ds;
+            uint32_t* counts_p = counts + p * K;
+            if (f) {
+                hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s,
+                                   idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, assign);
+                hipLaunchKernelGGL(k_kmeans_accum<true>, agrid, dim3(KM_THREADS), lds_accum, s, idx->X, idx->n,
+                                   idx->d, ds, p, K, assign, fx, sums_p, counts_p);
+            } else {
+                hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s,
+                                   idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, assign);
+                hipLaunchKernelGGL(k_kmeans_accum<false>, agrid, dim3(KM_THREADS), lds_accum, s, idx->X, idx->n,
+                                   idx->d, ds, p, K, assign, fx, sums_p, counts_p);
+            }
+            ANN_HIP_CHECK(hipGetLastError());
+        }
         const int ub = (PKd + 255) / 256;
         if (f)
             hipLaunchKernelGGL(k_kmeans_update<true>, dim3(ub), dim3(256), 0, s, idx->codebooks, sums, counts, P, K,
@@ -372,6 +411,7 @@ int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
     }
     ANN_HIP_CHECK(hipFreeAsync(sums, s));
     ANN_HIP_CHECK(hipFreeAsync(counts, s));
+    ANN_HIP_CHECK(hipFreeAsync(assign, s));
     return ANN_OK;
 }
 

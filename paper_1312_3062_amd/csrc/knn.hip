@@ -167,6 +167,222 @@ __global__ void __launch_bounds__(KNN_THREADS) k_knn_merge(const uint64_t* parti
     }
 }
 
+// ----------------------------------------------------------------------
+// u8 on matrix cores.  With u = x - 128 as int8 (x xor 0x80),
+//   |x - y|^2 = |u|^2 + |v|^2 - 2 u.v, exact in int32,
+// and u.v comes from v_mfma_i32_16x16x64_i8.  A workgroup of four wavefronts
+// owns 256 query rows, 64 per wavefront, whose operands stay in registers
+// for the whole scan; 64-candidate tiles stream through LDS (rows padded by
+// 16 bytes so that the 16 lanes reading one k-slice of 16 rows hit distinct
+// banks).  Lane l holds row l % 16 of a 16 x 64 operand block (bytes
+// 16 (l / 16) .. +15) and result rows 4 (l / 16) .. +3 of column l % 16.
+// The epilogue is two VALU operations per value: |v|^2 - 2 u.v against the
+// row's threshold (k-th best distance minus |u|^2).  The rare survivors go
+// through per-row LDS buckets to the lane that owns the row, which keeps its
+// best k keys sorted in registers.
+// ----------------------------------------------------------------------
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+
+constexpr int MQ_ROWS = 256;  // query rows per workgroup
+constexpr int MC_TILE = 64;   // candidates per LDS tile
+
+// |x - 128|^2 per row: sum x^2 - 256 sum x + 128^2 d
+__global__ void k_shifted_norms(const uint8_t* X, int64_t n, int d, uint32_t* out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4* r = reinterpret_cast<const uint4*>(X + i * d);
+    uint32_t sq = 0, sm = 0;
+    for (int c = 0; c < d / 16; ++c) {
+        const uint4 x = r[c];
+        sq = __builtin_amdgcn_udot4(x.x, x.x, sq, false);
+        sq = __builtin_amdgcn_udot4(x.y, x.y, sq, false);
+        sq = __builtin_amdgcn_udot4(x.z, x.z, sq, false);
+        sq = __builtin_amdgcn_udot4(x.w, x.w, sq, false);
+        sm = __builtin_amdgcn_udot4(x.x, 0x01010101u, sm, false);
+        sm = __builtin_amdgcn_udot4(x.y, 0x01010101u, sm, false);
+        sm = __builtin_amdgcn_udot4(x.z, 0x01010101u, sm, false);
+        sm = __builtin_amdgcn_udot4(x.w, 0x01010101u, sm, false);
+    }
+    out[i] = sq - 256u * sm + 16384u * uint32_t(d);
+}
+
+template <int KS, int KMAX>
+__global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32_t* xn, int64_t n, const uint8_t* Q,
+                                                  const uint32_t* qn_g, int64_t nq, int k, int excl,
+                                                  int32_t* out_ids, uint32_t* out_d, uint64_t* partial) {
+    constexpr int D = KS * 64;
+    constexpr int STRIDE = D + 16;
+    __shared__ __align__(16) uint8_t tile[MC_TILE * STRIDE];
+    __shared__ int cn_l[MC_TILE];
+    __shared__ uint64_t bucket[4][64][16];
+    __shared__ int bcnt[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t row0 = int64_t(blockIdx.x) * MQ_ROWS + w * 64;
+
+    v4i32 a[4][KS];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t r = min<int64_t>(row0 + rb * 16 + col, nq - 1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const uint4 v = *reinterpret_cast<const uint4*>(Q + r * D + s * 64 + kq * 16);
+            a[rb][s] = v4i32{int(v.x ^ 0x80808080u), int(v.y ^ 0x80808080u), int(v.z ^ 0x80808080u),
+                             int(v.w ^ 0x80808080u)};
+        }
+    }
+    // this lane's result rows: rb * 16 + 4 kq + t of the wavefront's 64
+    int qn[4][4], tq[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t r = row0 + rb * 16 + 4 * kq + t;
+            qn[rb][t] = r < nq ? int(qn_g[r]) : 0;
+            tq[rb][t] = 0x7FFFFFFF - qn[rb][t];
+        }
+    uint64_t top[KMAX];  // row row0 + lane, ascending
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) top[i] = KEY_EMPTY;
+    bcnt[w][lane] = 0;
+
+    const int64_t per = (n + gridDim.y - 1) / gridDim.y;
+    const int64_t jbeg = int64_t(blockIdx.y) * per;
+    const int64_t jend = min<int64_t>(n, jbeg + per);
+    for (int64_t j0 = jbeg; j0 < jend; j0 += MC_TILE) {
+        const int tj = int(min<int64_t>(MC_TILE, jend - j0));
+        __syncthreads();
+        {
+            constexpr int C16 = D / 16;
+            for (int i = threadIdx.x; i < MC_TILE * C16; i += 256) {
+                const int rr = i / C16, c = i - rr * C16;
+                uint4 v = make_uint4(0, 0, 0, 0);
+                if (rr < tj) v = *reinterpret_cast<const uint4*>(X + (j0 + rr) * D + c * 16);
+                v.x ^= 0x80808080u;
+                v.y ^= 0x80808080u;
+                v.z ^= 0x80808080u;
+                v.w ^= 0x80808080u;
+                *reinterpret_cast<uint4*>(tile + rr * STRIDE + c * 16) = v;
+            }
+            if (threadIdx.x < MC_TILE)
+                cn_l[threadIdx.x] = int(threadIdx.x) < tj ? int(xn[j0 + threadIdx.x]) : 0x3FFFFFFF;
+        }
+        __syncthreads();
+        const bool self_tile = excl && j0 < row0 + 64 && j0 + MC_TILE > row0;
+#pragma unroll
+        for (int cb = 0; cb < MC_TILE / 16; ++cb) {
+            v4i32 acc[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = v4i32{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const v4i32 b = *reinterpret_cast<const v4i32*>(tile + (cb * 16 + col) * STRIDE + s * 64 + kq * 16);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rb][s], b, acc[rb], 0, 0, 0);
+            }
+            const int jj = cb * 16 + col;
+            const int64_t j = j0 + jj;
+            const int cn = cn_l[jj];  // past the tile's end: too large to pass
+            bool any = false;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) any |= cn - 2 * acc[rb][t] <= tq[rb][t];
+            if (__ballot(any) == 0) continue;
+            // ---- slow path: survivors to their rows' buckets, owners merge
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int v = cn - 2 * acc[rb][t];
+                    const int wr = rb * 16 + 4 * kq + t;
+                    const bool me = self_tile && j == row0 + wr;
+                    if (v <= tq[rb][t] && jj < tj && !me) {
+                        const int slot = atomicAdd(&bcnt[w][wr], 1);
+                        bucket[w][wr][slot] = make_key(uint32_t(v + qn[rb][t]), uint32_t(j));
+                    }
+                }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            const int c = bcnt[w][lane];
+            for (int e = 0; e < c; ++e) topk_offer<KMAX>(top, bucket[w][lane][e]);
+            bcnt[w][lane] = 0;
+            uint64_t th = top[0];
+#pragma unroll
+            for (int i = 1; i < KMAX; ++i)
+                if (i == k - 1) th = top[i];
+            const int thr = th == KEY_EMPTY ? 0x7FFFFFFF : int(key_dist(th));
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) tq[rb][t] = __shfl(thr, rb * 16 + 4 * kq + t) - qn[rb][t];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    const int64_t qi = row0 + lane;
+    if (qi >= nq) return;
+    if (partial) {
+        uint64_t* dst = partial + (qi * gridDim.y + blockIdx.y) * k;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            if (i < k) dst[i] = top[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            if (i < k) {
+                const uint64_t v = top[i];
+                const bool ok = v != KEY_EMPTY;
+                out_ids[qi * k + i] = ok ? int32_t(key_id(v)) : -1;
+                out_d[qi * k + i] = ok ? key_dist(v) : 0x7FFFFFFFu;
+            }
+        }
+    }
+}
+
+template <int KS, int KMAX>
+int launch_knn_mfma(const void* d_x, int64_t n, const void* d_q, int64_t nq, int k, int excl, int32_t* d_ids,
+                    void* d_dists, hipStream_t s) {
+    const int64_t grid = ceil_div(nq, MQ_ROWS);
+    int slices = 1;
+    while (grid * slices < 1024 && slices < 256 && n / (slices * 2) >= MC_TILE * 16) slices *= 2;
+    uint32_t* norms = nullptr;
+    const bool same = d_q == d_x;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&norms), size_t(n + (same ? 0 : nq)) * 4, s));
+    uint32_t* qn = same ? norms : norms + n;
+    hipLaunchKernelGGL(k_shifted_norms, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                       static_cast<const uint8_t*>(d_x), n, KS * 64, norms);
+    if (!same)
+        hipLaunchKernelGGL(k_shifted_norms, dim3(unsigned(ceil_div(nq, 256))), dim3(256), 0, s,
+                           static_cast<const uint8_t*>(d_q), nq, KS * 64, qn);
+    uint64_t* partial = nullptr;
+    if (slices > 1)
+        ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), size_t(nq) * slices * k * sizeof(uint64_t), s));
+    hipLaunchKernelGGL((k_knn_mfma<KS, KMAX>), dim3(unsigned(grid), unsigned(slices)), dim3(256), 0, s,
+                       static_cast<const uint8_t*>(d_x), norms, n, static_cast<const uint8_t*>(d_q), qn, nq, k, excl,
+                       d_ids, static_cast<uint32_t*>(d_dists), partial);
+    ANN_HIP_CHECK(hipGetLastError());
+    if (slices > 1) {
+        hipLaunchKernelGGL((k_knn_merge<false, KMAX>), dim3(unsigned(ceil_div(nq, KNN_THREADS))), dim3(KNN_THREADS),
+                           0, s, partial, nq, slices, k, d_ids, static_cast<uint32_t*>(d_dists));
+        ANN_HIP_CHECK(hipGetLastError());
+        ANN_HIP_CHECK(hipFreeAsync(partial, s));
+    }
+    ANN_HIP_CHECK(hipFreeAsync(norms, s));
+    return ANN_OK;
+}
+
+template <int KMAX>
+int launch_knn_mfma_d(int d, const void* d_x, int64_t n, const void* d_q, int64_t nq, int k, int excl, int32_t* d_ids,
+                      void* d_dists, hipStream_t s) {
+    switch (d) {
+        case 64: return launch_knn_mfma<1, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+        case 128: return launch_knn_mfma<2, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+        case 192: return launch_knn_mfma<3, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+        default: return launch_knn_mfma<4, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+    }
+}
+
 template <bool FLOAT, int KMAX>
 int launch_knn_t(const void* d_x, int64_t n, int64_t row_bytes, const void* d_q, int64_t nq, int k, int excl,
                  int32_t* d_ids, void* d_dists, hipStream_t s) {
@@ -206,6 +422,10 @@ int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, in
     if (f) {
         if (k <= 16) return launch_knn_t<true, 16>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);
         return launch_knn_t<true, 32>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);
+    }
+    if (d % 64 == 0 && d <= 256) {  // matrix cores
+        if (k <= 16) return launch_knn_mfma_d<16>(d, d_x, n, d_q, nq, k, exclude_self, d_ids, d_dists, s);
+        return launch_knn_mfma_d<32>(d, d_x, n, d_q, nq, k, exclude_self, d_ids, d_dists, s);
     }
     if (k <= 16) return launch_knn_t<false, 16>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);
     return launch_knn_t<false, 32>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);

@@ -140,6 +140,35 @@ def test_knn_device_matches_oracle(tiny):
         np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), od)
 
 
+@pytest.mark.parametrize("n,nq,d,k,dups", [
+    (1000, 37, 128, 10, 0),     # matrix cores: ragged tile and query block
+    (4163, 300, 64, 32, 40),    # duplicated rows: ties broken by id
+    (777, 1, 192, 1, 5),
+    (2050, 257, 256, 16, 0),
+    (530, 70, 48, 7, 3),        # VALU path (d not a multiple of 64)
+])
+def test_knn_device_shapes_and_ties(n, nq, d, k, dups):
+    from paper_1312_3062_amd import knn_device
+    rng = np.random.default_rng(n + d)
+    X = rng.integers(0, 256, size=(n, d)).astype(np.uint8)
+    if dups:
+        X[rng.choice(n, dups, replace=False)] = X[rng.choice(n, dups)]
+    Q = np.concatenate([X[:nq // 2], rng.integers(0, 256, size=(nq - nq // 2, d)).astype(np.uint8)])
+    xd = torch.from_numpy(X).cuda()
+    ids, dd = knn_device(xd, torch.from_numpy(Q).cuda(), k)
+    torch.cuda.synchronize()
+    oi, od = oracle.knn(X, Q, k)
+    np.testing.assert_array_equal(ids.cpu().numpy(), oi)
+    np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), od)
+    # the graph form: each row's k nearest others
+    gi, gd = knn_device(xd, xd, k, exclude_self=True)
+    torch.cuda.synchronize()
+    rows = np.arange(0, n, max(1, n // 97))
+    oi, od = oracle.knn_graph_rows(X, rows, k)
+    np.testing.assert_array_equal(gi.cpu().numpy()[rows], oi)
+    np.testing.assert_array_equal(gd.cpu().numpy()[rows].astype(np.float64), od)
+
+
 def test_import_and_save_load_roundtrip(tiny, tiny_oracle, tmp_path):
     Index = _index_cls()
     X = tiny["X"]
