@@ -383,6 +383,225 @@ int launch_knn_mfma_d(int d, const void* d_x, int64_t n, const void* d_q, int64_
     }
 }
 
+// ----------------------------------------------------------------------
+// fp32 on matrix cores (v_mfma_f32_16x16x4f32).  Candidates are selected by
+// |q|^2 + |x|^2 - 2 q.x in fp32; the k kept per row are then measured again
+// as the fp32 sum of (q - x)^2 and re-sorted, so returned distances carry no
+// cancellation error.  A wavefront owns 16 query rows whose operands stay in
+// registers (lane l: row l % 16, dimensions 4 s + l / 16); 64-candidate
+// tiles stream through LDS in stages of 128 dimensions, rows padded by four
+// floats so that the 64 lanes of one step hit distinct banks.
+// ----------------------------------------------------------------------
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+constexpr int FQ_ROWS = 64;   // query rows per workgroup, 16 per wavefront
+
+__global__ void k_sq_norms_f32(const float* X, int64_t n, int d, float* out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4* r = reinterpret_cast<const float4*>(X + i * d);
+    float s = 0.f;
+    for (int c = 0; c < d / 4; ++c) {
+        const float4 x = r[c];
+        s = fmaf(x.x, x.x, s);
+        s = fmaf(x.y, x.y, s);
+        s = fmaf(x.z, x.z, s);
+        s = fmaf(x.w, x.w, s);
+    }
+    out[i] = s;
+}
+
+template <int KS4, int KMAX>
+__global__ void __launch_bounds__(256) k_knn_mfma_f32(const float* X, const float* xn, int64_t n, const float* Q,
+                                                      const float* qn_g, int64_t nq, int k, int excl,
+                                                      int32_t* out_ids, uint32_t* out_d, uint64_t* partial) {
+    constexpr int D = KS4 * 4;
+    constexpr int CH = D < 128 ? D : 128;  // dimensions per LDS stage
+    constexpr int NCH = D / CH;
+    constexpr int STRIDE = CH + 4;
+    __shared__ __align__(16) float tile[MC_TILE * STRIDE];
+    __shared__ float cn_l[MC_TILE];
+    __shared__ uint64_t bucket[4][16][MC_TILE];
+    __shared__ int bcnt[4][16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int64_t row0 = int64_t(blockIdx.x) * FQ_ROWS + w * 16;
+
+    float a[KS4];
+    {
+        const float* q = Q + min<int64_t>(row0 + col, nq - 1) * D + kq;
+#pragma unroll
+        for (int s = 0; s < KS4; ++s) a[s] = q[4 * s];
+    }
+    float qn[4], tq[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t r = row0 + 4 * kq + t;
+        qn[t] = r < nq ? qn_g[r] : 0.f;
+        tq[t] = __builtin_inff();
+    }
+    uint64_t top[KMAX];  // lanes 0..15: row row0 + lane, ascending
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) top[i] = KEY_EMPTY;
+    if (lane < 16) bcnt[w][lane] = 0;
+
+    const int64_t per = (n + gridDim.y - 1) / gridDim.y;
+    const int64_t jbeg = int64_t(blockIdx.y) * per;
+    const int64_t jend = min<int64_t>(n, jbeg + per);
+    for (int64_t j0 = jbeg; j0 < jend; j0 += MC_TILE) {
+        const int tj = int(min<int64_t>(MC_TILE, jend - j0));
+        v4f32 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = v4f32{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            __syncthreads();
+            constexpr int C4 = CH / 4;
+            for (int i = threadIdx.x; i < MC_TILE * C4; i += 256) {
+                const int rr = i / C4, c = i - rr * C4;
+                float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (rr < tj) v = *reinterpret_cast<const float4*>(X + (j0 + rr) * D + ch * CH + c * 4);
+                *reinterpret_cast<float4*>(tile + rr * STRIDE + c * 4) = v;
+            }
+            if (ch == 0 && threadIdx.x < MC_TILE)
+                cn_l[threadIdx.x] = int(threadIdx.x) < tj ? xn[j0 + threadIdx.x] : __builtin_inff();
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < C4; ++s) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const float b = tile[(cb * 16 + col) * STRIDE + 4 * s + kq];
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ch * C4 + s], b, acc[cb], 0, 0, 0);
+                }
+            }
+        }
+        bool any = false;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const float cn = cn_l[cb * 16 + col];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) any |= fmaf(-2.f, acc[cb][t], cn) <= tq[t];
+        }
+        if (__ballot(any) == 0) continue;
+        const bool self_tile = excl && j0 < row0 + 16 && j0 + MC_TILE > row0;
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int jj = cb * 16 + col;
+            const int64_t j = j0 + jj;
+            const float cn = cn_l[jj];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float v = fmaf(-2.f, acc[cb][t], cn);
+                const int wr = 4 * kq + t;
+                const bool me = self_tile && j == row0 + wr;
+                if (v <= tq[t] && jj < tj && !me) {
+                    const int slot = atomicAdd(&bcnt[w][wr], 1);
+                    bucket[w][wr][slot] = make_key(__float_as_uint(fmaxf(v + qn[t], 0.f)), uint32_t(j));
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        float thr = __builtin_inff();
+        if (lane < 16) {
+            const int c = bcnt[w][lane];
+            for (int e = 0; e < c; ++e) topk_offer<KMAX>(top, bucket[w][lane][e]);
+            bcnt[w][lane] = 0;
+            uint64_t th = top[0];
+#pragma unroll
+            for (int i = 1; i < KMAX; ++i)
+                if (i == k - 1) th = top[i];
+            if (th != KEY_EMPTY) thr = __uint_as_float(key_dist(th));
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) tq[t] = __shfl(thr, 4 * kq + t) - qn[t];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+    const int64_t qi = row0 + lane;
+    if (lane >= 16 || qi >= nq) return;
+    // the kept keys measured again as sum (q - x)^2, then sorted
+    uint64_t fin[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) fin[i] = KEY_EMPTY;
+    const float4* qr = reinterpret_cast<const float4*>(Q + qi * D);
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+        if (i < k && top[i] != KEY_EMPTY) {
+            const uint32_t j = key_id(top[i]);
+            const float4* xr = reinterpret_cast<const float4*>(X + int64_t(j) * D);
+            float e = 0.f;
+            for (int c = 0; c < D / 4; ++c) {
+                const float4 q = qr[c], x = xr[c];
+                float t;
+                t = q.x - x.x; e = fmaf(t, t, e);
+                t = q.y - x.y; e = fmaf(t, t, e);
+                t = q.z - x.z; e = fmaf(t, t, e);
+                t = q.w - x.w; e = fmaf(t, t, e);
+            }
+            topk_offer<KMAX>(fin, make_key(__float_as_uint(e), j));
+        }
+    }
+    if (partial) {
+        uint64_t* dst = partial + (qi * gridDim.y + blockIdx.y) * k;
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            if (i < k) dst[i] = fin[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            if (i < k) {
+                const uint64_t v = fin[i];
+                const bool ok = v != KEY_EMPTY;
+                out_ids[qi * k + i] = ok ? int32_t(key_id(v)) : -1;
+                out_d[qi * k + i] = ok ? key_dist(v) : 0x7F800000u;
+            }
+        }
+    }
+}
+
+template <int KS4, int KMAX>
+int launch_knn_mfma_f32(const void* d_x, int64_t n, const void* d_q, int64_t nq, int k, int excl, int32_t* d_ids,
+                        void* d_dists, hipStream_t s) {
+    const int64_t grid = ceil_div(nq, FQ_ROWS);
+    int slices = 1;
+    while (grid * slices < 1024 && slices < 256 && n / (slices * 2) >= MC_TILE * 16) slices *= 2;
+    float* norms = nullptr;
+    const bool same = d_q == d_x;
+    ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&norms), size_t(n + (same ? 0 : nq)) * 4, s));
+    float* qn = same ? norms : norms + n;
+    hipLaunchKernelGGL(k_sq_norms_f32, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                       static_cast<const float*>(d_x), n, KS4 * 4, norms);
+    if (!same)
+        hipLaunchKernelGGL(k_sq_norms_f32, dim3(unsigned(ceil_div(nq, 256))), dim3(256), 0, s,
+                           static_cast<const float*>(d_q), nq, KS4 * 4, qn);
+    uint64_t* partial = nullptr;
+    if (slices > 1)
+        ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), size_t(nq) * slices * k * sizeof(uint64_t), s));
+    hipLaunchKernelGGL((k_knn_mfma_f32<KS4, KMAX>), dim3(unsigned(grid), unsigned(slices)), dim3(256), 0, s,
+                       static_cast<const float*>(d_x), norms, n, static_cast<const float*>(d_q), qn, nq, k, excl,
+                       d_ids, static_cast<uint32_t*>(d_dists), partial);
+    ANN_HIP_CHECK(hipGetLastError());
+    if (slices > 1) {
+        hipLaunchKernelGGL((k_knn_merge<true, KMAX>), dim3(unsigned(ceil_div(nq, KNN_THREADS))), dim3(KNN_THREADS),
+                           0, s, partial, nq, slices, k, d_ids, static_cast<uint32_t*>(d_dists));
+        ANN_HIP_CHECK(hipGetLastError());
+        ANN_HIP_CHECK(hipFreeAsync(partial, s));
+    }
+    ANN_HIP_CHECK(hipFreeAsync(norms, s));
+    return ANN_OK;
+}
+
+template <int KMAX>
+int launch_knn_mfma_f32_d(int d, const void* d_x, int64_t n, const void* d_q, int64_t nq, int k, int excl,
+                          int32_t* d_ids, void* d_dists, hipStream_t s) {
+    switch (d) {
+        case 128: return launch_knn_mfma_f32<32, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+        case 256: return launch_knn_mfma_f32<64, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+        default: return launch_knn_mfma_f32<96, KMAX>(d_x, n, d_q, nq, k, excl, d_ids, d_dists, s);
+    }
+}
+
 template <bool FLOAT, int KMAX>
 int launch_knn_t(const void* d_x, int64_t n, int64_t row_bytes, const void* d_q, int64_t nq, int k, int excl,
                  int32_t* d_ids, void* d_dists, hipStream_t s) {
@@ -420,6 +639,10 @@ int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, in
     ANN_REQUIRE(f || d <= 512, "ann_knn_device: u8 dimension above 512");
     if (nq == 0) return ANN_OK;
     if (f) {
+        if (d == 128 || d == 256 || d == 384) {  // matrix cores
+            if (k <= 16) return launch_knn_mfma_f32_d<16>(d, d_x, n, d_q, nq, k, exclude_self, d_ids, d_dists, s);
+            return launch_knn_mfma_f32_d<32>(d, d_x, n, d_q, nq, k, exclude_self, d_ids, d_dists, s);
+        }
         if (k <= 16) return launch_knn_t<true, 16>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);
         return launch_knn_t<true, 32>(d_x, n, row_bytes, d_q, nq, k, exclude_self, d_ids, d_dists, s);
     }

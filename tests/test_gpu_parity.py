@@ -169,6 +169,29 @@ def test_knn_device_shapes_and_ties(n, nq, d, k, dups):
     np.testing.assert_array_equal(gd.cpu().numpy()[rows].astype(np.float64), od)
 
 
+@pytest.mark.parametrize("n,nq,d,k", [(3000, 70, 384, 10), (2100, 300, 128, 32), (900, 5, 256, 1), (700, 40, 96, 16)])
+def test_knn_device_f32_within_tolerance(n, nq, d, k):
+    """fp32 kNN (matrix cores for d in {128, 256, 384}) against the fp64 oracle:
+    returned distances within 1e-5 relative, ids equal except where fp32
+    rounding reorders a near tie."""
+    from paper_1312_3062_amd import knn_device
+    rng = np.random.default_rng(d + k)
+    X = np.abs(rng.standard_normal((n, d))).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Q = np.abs(rng.standard_normal((nq, d))).astype(np.float32)
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    xd = torch.from_numpy(X).cuda()
+    for q, excl in ((Q, False), (X, True)):
+        ids, dd = knn_device(xd, torch.from_numpy(q).cuda(), k, exclude_self=excl)
+        torch.cuda.synchronize()
+        ids, dd = ids.cpu().numpy(), dd.cpu().numpy().astype(np.float64)
+        oi, od = oracle.knn(X, q, k, exclude=np.arange(len(q)) if excl else None)
+        np.testing.assert_allclose(dd, od, rtol=1e-5)
+        ex = ((X[ids].astype(np.float64) - q.astype(np.float64)[:, None, :]) ** 2).sum(2)
+        np.testing.assert_allclose(dd, ex, rtol=1e-5)
+        assert (ids == oi).mean() >= 0.99
+
+
 def test_import_and_save_load_roundtrip(tiny, tiny_oracle, tmp_path):
     Index = _index_cls()
     X = tiny["X"]
