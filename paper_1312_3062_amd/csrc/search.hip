@@ -77,6 +77,8 @@ struct SearchArgs {
     int gms_cap;         // capacity of a slot
     int nslots;          // slots; the re-run kernel's workgroup b owns slot b
     uint32_t* slot_bits; // main kernel: bitmap of the slots in use (cleared at launch)
+    int t_lo, t_hi;          // budget class served by this launch (inclusive); t_hi = Tmax
+    int Tall;                // largest budget of the whole request: clamp and trace row stride
     uint32_t* work_counter;  // persistent launch: next work item (null: grid-stride)
     const uint32_t* perm;    // optional serving order of the queries
     // LDS layout (byte offsets)
@@ -611,7 +613,8 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         const int64_t qi = RERUN ? int64_t(a.ovf_list[wi]) : (a.perm ? int64_t(a.perm[wi]) : wi);
         // per-query values are clamped to the launch maxima that sized the buffers
         const int k = a.ks ? min(max(a.ks[qi], 1), a.kmax) : a.kmax;
-        const int T = a.Ts ? min(max(a.Ts[qi], 0), a.Tmax) : a.Tmax;
+        const int T = a.Ts ? min(max(a.Ts[qi], 0), a.Tall) : a.Tall;
+        if (!RERUN && (T < a.t_lo || T > a.t_hi)) continue;  // another budget class's query
         const int rcap = (MODE == MODE_BF16) ? max(k, a.rerank_k) : k;
 
         // ---- load the query, clear the distance cache
@@ -656,7 +659,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         // the lanes with `ev` hold evaluated keys (rank r in adjacency order):
         // record them and offer them to the result set and the main queue
         auto offer = [&](uint64_t key, bool ev) {
-            if (a.trace && ev) a.trace[qi * a.Tmax + t + r] = int32_t(key_id(key));
+            if (a.trace && ev) a.trace[qi * a.Tall + t + r] = int32_t(key_id(key));
             const uint64_t rworst = rn < rcap ? KEY_EMPTY : reg_get<KPL>(Rv, rn - 1);
             const bool ra = ev && key < rworst;
             if (__ballot(ra)) reg_insert<KPL>(Rv, rn, rcap, key, ra, lane);
@@ -1019,7 +1022,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             }
         }
         if (a.trace)
-            for (int i = t + lane; i < a.Tmax; i += WAVE) a.trace[qi * a.Tmax + i] = -1;
+            for (int i = t + lane; i < a.Tall; i += WAVE) a.trace[qi * a.Tall + i] = -1;
         if (a.stats && lane == 0) {
             int32_t* s = a.stats + qi * ANN_NSTATS;
             s[ANN_STAT_EVALS] = t;
@@ -1171,9 +1174,8 @@ struct Plan {
     bool bf16 = false, is_f32 = false;
     int grid2 = 128;
     int64_t gcap = 0;
-    size_t slot_bytes = 0, fixed_bytes = 0;
+    size_t slot_bytes = 0;
     int max_slots = 0;
-    size_t ws_bytes = 0;  // with max_slots slots
 };
 
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
@@ -1217,6 +1219,9 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.Ts = s.d_T;
     a.kmax = s.kmax;
     a.Tmax = s.Tmax;
+    a.Tall = s.Tmax;
+    a.t_lo = 0;
+    a.t_hi = s.Tmax;
     a.L = s.L;
     a.rerank_k = s.rerank_k > 0 ? s.rerank_k : s.kmax;
     a.out_ids = s.d_ids;
@@ -1259,103 +1264,158 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     int64_t slots = s.Tmax > 2048 ? resident : kSmallBudgetSlots;
     slots = std::min<int64_t>(slots, int64_t(kMaxSlotBytes / pl.slot_bytes));
     pl.max_slots = int(std::max<int64_t>(1, std::min<int64_t>(slots, s.nq)));
-    pl.fixed_bytes = (256 + round16(size_t(ceil_div(pl.max_slots, 32)) * 4) + round16(size_t(s.nq) * 4) + 256 +
-                      round16(size_t(s.nq) * 4) + 63) & ~size_t(63);
-    pl.ws_bytes = pl.fixed_bytes + size_t(pl.max_slots) * pl.slot_bytes;
     return ANN_OK;
 }
 
-int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes) {
+// Budget classes.  With per-query budgets a launch serves up to three classes
+// (T <= 512, T <= 2048, larger) by one kernel each, in turn on the stream,
+// each sized (LDS, multi-sequence capacity, slots) by its own largest budget:
+// a few long queries then do not shrink the residency of the many short ones.
+struct ClassPlan {
     Plan pl;
-    int rc = make_plan(s, pl);
+    int t_lo, t_hi;
+};
+
+static int make_class_plans(const SearchLaunch& s, std::vector<ClassPlan>& out) {
+    out.clear();
+    std::vector<std::pair<int, int>> ranges;
+    if (!s.d_T || s.Tmax <= 512) {
+        ranges.push_back({0, s.Tmax});
+    } else {
+        if (s.Tmax > 2048) ranges.push_back({2049, s.Tmax});
+        ranges.push_back({513, std::min(s.Tmax, 2048)});
+        ranges.push_back({0, 512});
+    }
+    for (auto r : ranges) {
+        SearchLaunch sc = s;
+        sc.Tmax = r.second;
+        ClassPlan c;
+        int rc = make_plan(sc, c.pl);
+        if (rc) return rc;
+        c.pl.a.Tall = c.pl.a2.Tall = s.Tmax;
+        c.pl.a.t_lo = c.pl.a2.t_lo = r.first;
+        c.pl.a.t_hi = c.pl.a2.t_hi = r.second;
+        out.push_back(c);
+    }
+    return ANN_OK;
+}
+
+// workspace: counters | slot bitmap | overflow list | order buckets | order |
+// global multi-sequence slots (the largest count any class uses)
+struct WsLayout {
+    int max_slots = 0, bit_words = 0;
+    size_t slot_bytes = 0, fixed = 0, total = 0;
+};
+
+static WsLayout ws_layout(const std::vector<ClassPlan>& cl, int64_t nq) {
+    WsLayout L;
+    for (const auto& c : cl) L.max_slots = std::max(L.max_slots, c.pl.max_slots);
+    L.slot_bytes = cl.front().pl.slot_bytes;
+    L.bit_words = int(ceil_div(L.max_slots, 32));
+    L.fixed = (256 + round16(size_t(L.bit_words) * 4) + round16(size_t(nq) * 4) + 256 + round16(size_t(nq) * 4) + 63) &
+              ~size_t(63);
+    L.total = L.fixed + size_t(L.max_slots) * L.slot_bytes;
+    return L;
+}
+
+int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes) {
+    std::vector<ClassPlan> cl;
+    int rc = make_class_plans(s, cl);
     if (rc) return rc;
-    *bytes = int64_t(pl.ws_bytes);
+    *bytes = int64_t(ws_layout(cl, s.nq).total);
     return ANN_OK;
 }
 
 int launch_search(const SearchLaunch& s) {
     if (s.nq == 0) return ANN_OK;
-    Plan pl;
-    int rc = make_plan(s, pl);
+    std::vector<ClassPlan> cl;
+    int rc = make_class_plans(s, cl);
     if (rc) return rc;
-    SearchArgs& a = pl.a;
-    SearchArgs& a2 = pl.a2;
+    const WsLayout L = ws_layout(cl, s.nq);
 
     int dev = 0, max_lds = 0, cus = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (pl.lds1 > max_lds)
-        return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(pl.lds1) +
-                                               " bytes of LDS per query, more than the device's " +
-                                               std::to_string(max_lds) + " (lower budget or k)");
+    for (const auto& c : cl)
+        if (c.pl.lds1 > max_lds)
+            return set_error(ANN_EUNSUPPORTED, "search needs " + std::to_string(c.pl.lds1) +
+                                                   " bytes of LDS per query, more than the device's " +
+                                                   std::to_string(max_lds) + " (lower budget or k)");
 
     uint8_t* w = static_cast<uint8_t*>(s.workspace);
     const bool own = w == nullptr;
-    int nslots = pl.max_slots;
+    int avail = L.max_slots;
     if (own) {
-        ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), pl.ws_bytes, s.stream));
+        ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), L.total, s.stream));
     } else {
-        ANN_REQUIRE(s.workspace_bytes >= int64_t(pl.fixed_bytes + pl.slot_bytes),
+        ANN_REQUIRE(s.workspace_bytes >= int64_t(L.fixed + L.slot_bytes),
                     "search: workspace too small (" + std::to_string(s.workspace_bytes) + " bytes, at least " +
-                        std::to_string(pl.fixed_bytes + pl.slot_bytes) + " needed)");
+                        std::to_string(L.fixed + L.slot_bytes) + " needed)");
         ANN_REQUIRE((reinterpret_cast<uintptr_t>(w) & 15) == 0, "search: workspace must be 16-byte aligned");
-        nslots = int(std::min<int64_t>(pl.max_slots, (s.workspace_bytes - int64_t(pl.fixed_bytes)) /
-                                                         int64_t(pl.slot_bytes)));
+        avail = int(std::min<int64_t>(L.max_slots, (s.workspace_bytes - int64_t(L.fixed)) / int64_t(L.slot_bytes)));
     }
-    pl.grid2 = std::min(pl.grid2, nslots);
     // [0] overflow count, [1] work counter
     uint32_t* counters = reinterpret_cast<uint32_t*>(w);
     size_t o = 256;
-    const int bit_words = ceil_div(pl.max_slots, 32);
     uint32_t* slot_bits = reinterpret_cast<uint32_t*>(w + o);  // global slots in use
-    o += round16(size_t(bit_words) * 4);
+    o += round16(size_t(L.bit_words) * 4);
     uint32_t* ovf_list = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
     uint32_t* buckets = reinterpret_cast<uint32_t*>(w + o);  // 32 starts + 32 cursors
     o += 256;
     uint32_t* perm = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
-    o = (o + 63) & ~size_t(63);  // == pl.fixed_bytes
+    o = (o + 63) & ~size_t(63);  // == L.fixed
     uint8_t* gheap = w + o;
 
-    a.ovf_count = a2.ovf_count = counters;
-    a.ovf_list = a2.ovf_list = ovf_list;
-    a.gheap = a2.gheap = gheap;
-    a.gms_cap = a2.gms_cap = int(pl.gcap);
-    a.nslots = a2.nslots = nslots;
-    a.slot_bits = a2.slot_bits = slot_bits;
-    a2.ms_cap = a.ms_cap;
-    a.work_counter = s.persistent ? counters + 1 : nullptr;
-    a2.work_counter = nullptr;
-    a.perm = nullptr;
-    // counters and order buckets are cleared by a kernel (no memset nodes in captured graphs)
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, counters, 64);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, slot_bits, bit_words);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, buckets, 64);
+    // the serving order (longest budgets first) is shared by the classes;
+    // buffers are cleared by a kernel (no memset nodes in captured graphs)
+    const uint32_t* order = nullptr;
     if (s.persistent && s.order && s.d_T) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, buckets, 64);
         const unsigned gb = unsigned(ceil_div(s.nq, 256));
         hipLaunchKernelGGL(k_order_count, dim3(gb), dim3(256), 0, s.stream, s.d_T, s.nq, buckets);
         hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(WAVE), 0, s.stream, buckets);
         hipLaunchKernelGGL(k_order_scatter, dim3(gb), dim3(256), 0, s.stream, s.d_T, s.nq, buckets, buckets + 32,
                            perm);
-        a.perm = perm;
+        order = perm;
     }
 
     const Grid g{std::min<int64_t>(s.nq, int64_t(1) << 30), s.waves_per_cu, cus};
     const ann_index* idx = s.idx;
-    if (!pl.is_f32) {
-        if (idx->row_bytes == 128)
-            rc = launch_kpl<MODE_U8, 8>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
-        else
-            rc = launch_kpl<MODE_U8, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
-    } else if (pl.bf16) {
-        rc = launch_kpl<MODE_BF16, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
-    } else {
-        rc = launch_kpl<MODE_F32, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+    for (auto& c : cl) {
+        Plan& pl = c.pl;
+        SearchArgs& a = pl.a;
+        SearchArgs& a2 = pl.a2;
+        const int nslots = std::min(pl.max_slots, avail);
+        pl.grid2 = std::min(pl.grid2, nslots);
+        a.ovf_count = a2.ovf_count = counters;
+        a.ovf_list = a2.ovf_list = ovf_list;
+        a.gheap = a2.gheap = gheap;
+        a.gms_cap = a2.gms_cap = int(pl.gcap);
+        a.nslots = a2.nslots = nslots;
+        a.slot_bits = a2.slot_bits = slot_bits;
+        a2.ms_cap = a.ms_cap;
+        a.work_counter = s.persistent ? counters + 1 : nullptr;
+        a2.work_counter = nullptr;
+        a.perm = order;
+        a2.perm = nullptr;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, counters, 64);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(WAVE), 0, s.stream, slot_bits, L.bit_words);
+        if (!pl.is_f32) {
+            if (idx->row_bytes == 128)
+                rc = launch_kpl<MODE_U8, 8>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+            else
+                rc = launch_kpl<MODE_U8, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+        } else if (pl.bf16) {
+            rc = launch_kpl<MODE_BF16, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+        } else {
+            rc = launch_kpl<MODE_F32, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+        }
+        if (rc) return rc;
+        ANN_HIP_CHECK(hipGetLastError());
     }
-    if (rc) return rc;
-    ANN_HIP_CHECK(hipGetLastError());
     if (own) ANN_HIP_CHECK(hipFreeAsync(w, s.stream));
     return ANN_OK;
 }
