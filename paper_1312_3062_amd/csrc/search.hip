@@ -1179,6 +1179,7 @@ struct Plan {
 };
 
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
+constexpr int kLdsGranule = 2560;  // LDS allocation granule of a workgroup (160 KB / 64)
 
 // Global slots for multi-sequence state that outgrows LDS.  Up to T = 2048
 // few queries need one and 256 slots serve them; above it most queries move,
@@ -1230,9 +1231,11 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.trace = s.d_trace;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates); buckets for a final load of about 0.8
+    // than it evaluates); buckets for a final load of about 0.8.  The
+    // distance cache (cleared when half full) gets at least 64 buckets and
+    // grows into the slack of the last LDS granule (below).
     a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
-    a.dc_buckets = 96;  // distance cache: 384 slots, cleared when half full
+    a.dc_buckets = 64;
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
     // multi-sequence capacity in LDS (materialised side elements and outer
@@ -1248,9 +1251,17 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     const int PK = idx->P * idx->K;
     pl.rcap = pl.bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
     ANN_REQUIRE(pl.rcap <= 1024, "search: k (or rerank_k) above 1024");
-    pl.a2 = a;
     const int lpr = pl.is_f32 ? (pl.bf16 ? Traits<MODE_BF16>::LPR : Traits<MODE_F32>::LPR) : Traits<MODE_U8>::LPR;
     pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+    {
+        // LDS is allocated to a workgroup in granules of 2.5 KB: a larger
+        // distance cache that stays within the same granules costs no
+        // residency (a bucket of keys and values is 32 bytes)
+        const int slack = int(ceil_div(pl.lds1, kLdsGranule) * kLdsGranule) - pl.lds1;
+        a.dc_buckets = uint32_t(std::min(128, 64 + slack / 32));
+        pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+    }
+    pl.a2 = a;
     pl.lds2 = layout(pl.a2, qbytes, PK, pl.rcap, false, pl.bf16, lpr);
 
     // workspace: counters | slot bitmap | overflow list | order buckets |
