@@ -82,6 +82,7 @@ struct SearchArgs {
     uint32_t* work_counter;  // persistent launch: next work item (null: grid-stride)
     const uint32_t* perm;    // optional serving order of the queries
     // LDS layout (byte offsets)
+    int o_mrg;  // merge buffer of the register queues
     int o_q, o_sv, o_perm, o_ms, o_rk, o_ro, o_rl, o_sk, o_pid, o_pd, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd,
         o_sc;
 };
@@ -362,6 +363,41 @@ __device__ inline void reg_insert(uint64_t (&v)[KPL], int& n, int cap, uint64_t 
     }
 }
 
+// The same offer for one key per lane (cap <= 64), all new keys at once:
+// the result is the smallest min(cap, n + m) of the old and new keys,
+// sorted, which is what offering them one at a time to a bounded set that
+// evicts its largest key leaves.  Each key's place is its rank among old and
+// new keys, counted in one pass over the new keys; the keys are written to
+// their places in LDS (buf: 64 keys for this wavefront) and read back.
+__device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool isnew, int lane, uint64_t* buf) {
+    uint64_t nm = __ballot(isnew);
+    const int m = __popcll(nm);
+    const bool old = lane < n;
+    int above = 0;      // old key: new keys below it
+    int new_below = 0;  // new key: new keys below it
+    int old_below = 0;  // new key: old keys below it
+    while (nm) {
+        const int j = __builtin_ctzll(nm);
+        nm &= nm - 1;
+        const uint64_t xj = readlane64(x, j);
+        const bool lt = old && xj < v;
+        above += lt;
+        new_below += isnew && xj < x;
+        const int ob = n - __popcll(__ballot(lt));  // keys are distinct
+        old_below = lane == j ? ob : old_below;
+    }
+    const int po = lane + above, pn = old_below + new_below;
+    if (old && po < cap) buf[po] = v;
+    if (isnew && pn < cap) buf[pn] = x;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    const int total = min(cap, n + m);
+    v = lane < total ? buf[lane] : KEY_EMPTY;
+    n = total;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // remove and return the smallest key (n > 0)
 __device__ inline uint64_t reg_pop_front(uint64_t (&v)[1], int& n) {
     const uint64_t x = readlane64(v[0], 0);
@@ -578,6 +614,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     uint32_t* gid = reinterpret_cast<uint32_t*>(lds + a.o_gid);
     uint32_t* gd = reinterpret_cast<uint32_t*>(lds + a.o_gd);
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
+    uint64_t* mrg = reinterpret_cast<uint64_t*>(lds + a.o_mrg);  // merge buffer, 64 keys
 
     const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, a.K, a.P);
     MSeqMem msm;
@@ -662,10 +699,15 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
             if (a.trace && ev) a.trace[qi * a.Tall + t + r] = int32_t(key_id(key));
             const uint64_t rworst = rn < rcap ? KEY_EMPTY : reg_get<KPL>(Rv, rn - 1);
             const bool ra = ev && key < rworst;
-            if (__ballot(ra)) reg_insert<KPL>(Rv, rn, rcap, key, ra, lane);
+            if (__ballot(ra)) {
+                if constexpr (KPL == 1)
+                    reg_merge1(Rv[0], rn, rcap, key, ra, lane, mrg);
+                else
+                    reg_insert<KPL>(Rv, rn, rcap, key, ra, lane);
+            }
             const uint64_t qworst = qn < a.L ? KEY_EMPTY : readlane64(Qv[0], qn - 1);
             const bool qa = ev && key < qworst;
-            if (__ballot(qa)) reg_insert<1>(Qv, qn, a.L, key, qa, lane);
+            if (__ballot(qa)) reg_merge1(Qv[0], qn, a.L, key, qa, lane, mrg);
         };
 
         while (t < T) {
@@ -1130,6 +1172,7 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
     a.o_gid = take(bf16 ? std::max(WAVE * 4, rcap * 8) : (lpr > 1 ? WAVE * 4 : 8), 8);
     a.o_gd = take(lpr > 1 ? WAVE * 4 : 8, 8);
     a.o_sc = take(16 * 4, 8);
+    a.o_mrg = take(WAVE * 8, 8);
     return align_up(off, 16);
 }
 
