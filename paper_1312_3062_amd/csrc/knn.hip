@@ -212,8 +212,10 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
                                                   int32_t* out_ids, uint32_t* out_d, uint64_t* partial) {
     constexpr int D = KS * 64;
     constexpr int STRIDE = D + 16;
-    __shared__ __align__(16) uint8_t tile[MC_TILE * STRIDE];
-    __shared__ int cn_l[MC_TILE];
+    constexpr int C16 = D / 16;                       // 16-byte chunks per row
+    constexpr int PER = MC_TILE * C16 / 256;          // chunks per thread per tile
+    __shared__ __align__(16) uint8_t tile[2][MC_TILE * STRIDE];  // double buffer
+    __shared__ int cn_l[2][MC_TILE];
     __shared__ uint64_t bucket[4][64][16];
     __shared__ int bcnt[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -249,25 +251,44 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
     const int64_t per = (n + gridDim.y - 1) / gridDim.y;
     const int64_t jbeg = int64_t(blockIdx.y) * per;
     const int64_t jend = min<int64_t>(n, jbeg + per);
-    for (int64_t j0 = jbeg; j0 < jend; j0 += MC_TILE) {
+    // the next tile is loaded into registers while the current one is used
+    uint4 pre[PER];
+    int pcn = 0;
+    auto fetch = [&](int64_t j0) {
         const int tj = int(min<int64_t>(MC_TILE, jend - j0));
-        __syncthreads();
-        {
-            constexpr int C16 = D / 16;
-            for (int i = threadIdx.x; i < MC_TILE * C16; i += 256) {
-                const int rr = i / C16, c = i - rr * C16;
-                uint4 v = make_uint4(0, 0, 0, 0);
-                if (rr < tj) v = *reinterpret_cast<const uint4*>(X + (j0 + rr) * D + c * 16);
-                v.x ^= 0x80808080u;
-                v.y ^= 0x80808080u;
-                v.z ^= 0x80808080u;
-                v.w ^= 0x80808080u;
-                *reinterpret_cast<uint4*>(tile + rr * STRIDE + c * 16) = v;
-            }
-            if (threadIdx.x < MC_TILE)
-                cn_l[threadIdx.x] = int(threadIdx.x) < tj ? int(xn[j0 + threadIdx.x]) : 0x3FFFFFFF;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * 256;
+            const int rr = i / C16, c = i - rr * C16;
+            pre[u] = rr < tj ? *reinterpret_cast<const uint4*>(X + (j0 + rr) * D + c * 16) : make_uint4(0, 0, 0, 0);
         }
-        __syncthreads();
+        if (threadIdx.x < MC_TILE) pcn = int(threadIdx.x) < tj ? int(xn[j0 + threadIdx.x]) : 0x3FFFFFFF;
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int i = threadIdx.x + u * 256;
+            const int rr = i / C16, c = i - rr * C16;
+            uint4 v = pre[u];
+            v.x ^= 0x80808080u;
+            v.y ^= 0x80808080u;
+            v.z ^= 0x80808080u;
+            v.w ^= 0x80808080u;
+            *reinterpret_cast<uint4*>(tile[buf] + rr * STRIDE + c * 16) = v;
+        }
+        if (threadIdx.x < MC_TILE) cn_l[buf][threadIdx.x] = pcn;
+    };
+    if (jbeg < jend) {
+        fetch(jbeg);
+        stash(0);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t j0 = jbeg; j0 < jend; j0 += MC_TILE, cur ^= 1) {
+        const int tj = int(min<int64_t>(MC_TILE, jend - j0));
+        const bool more = j0 + MC_TILE < jend;
+        if (more) fetch(j0 + MC_TILE);
+        const uint8_t* tl = tile[cur];
         const bool self_tile = excl && j0 < row0 + 64 && j0 + MC_TILE > row0;
 #pragma unroll
         for (int cb = 0; cb < MC_TILE / 16; ++cb) {
@@ -276,13 +297,13 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
             for (int rb = 0; rb < 4; ++rb) acc[rb] = v4i32{0, 0, 0, 0};
 #pragma unroll
             for (int s = 0; s < KS; ++s) {
-                const v4i32 b = *reinterpret_cast<const v4i32*>(tile + (cb * 16 + col) * STRIDE + s * 64 + kq * 16);
+                const v4i32 b = *reinterpret_cast<const v4i32*>(tl + (cb * 16 + col) * STRIDE + s * 64 + kq * 16);
 #pragma unroll
                 for (int rb = 0; rb < 4; ++rb) acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rb][s], b, acc[rb], 0, 0, 0);
             }
             const int jj = cb * 16 + col;
             const int64_t j = j0 + jj;
-            const int cn = cn_l[jj];  // past the tile's end: too large to pass
+            const int cn = cn_l[cur][jj];  // past the tile's end: too large to pass
             bool any = false;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
@@ -319,6 +340,8 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
             __builtin_amdgcn_wave_barrier();
         }
+        if (more) stash(cur ^ 1);
+        __syncthreads();
     }
     const int64_t qi = row0 + lane;
     if (qi >= nq) return;
