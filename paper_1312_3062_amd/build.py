@@ -24,6 +24,9 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}",
     # packed fp32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results go to ordinary VGPRs, which the epilogues read
+    # without an accumulator-register copy per value
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

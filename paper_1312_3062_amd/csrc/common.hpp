@@ -52,6 +52,15 @@ __device__ inline uint32_t f_bits(float f) { return __float_as_uint(f); }
 __device__ inline int lane_id() { return __lane_id(); }
 
 // number of set bits of `mask` below this lane
+// Order LDS accesses of one wavefront around a cross-lane exchange through
+// LDS.  A wavefront's LDS instructions execute in issue order, so it only has
+// to keep the compiler from moving memory operations across this point; it
+// does not wait for outstanding global loads (a fence would).
+__device__ inline void lds_wave_order() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
 __device__ inline int lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0));
 }

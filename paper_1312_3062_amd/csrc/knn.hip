@@ -233,16 +233,15 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
                              int(v.w ^ 0x80808080u)};
         }
     }
-    // this lane's result rows: rb * 16 + 4 kq + t of the wavefront's 64
-    int qn[4][4], tq[4][4];
+    // this lane's result rows: rb * 16 + 4 kq + t of the wavefront's 64.  A
+    // candidate passes when 2 u.v - |v|^2 >= nt = |u|^2 - (k-th best distance)
+    auto qnorm = [&](int wr) { return row0 + wr < nq ? int(qn_g[row0 + wr]) : 0; };
+    int nt[4][4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t r = row0 + rb * 16 + 4 * kq + t;
-            qn[rb][t] = r < nq ? int(qn_g[r]) : 0;
-            tq[rb][t] = 0x7FFFFFFF - qn[rb][t];
-        }
+        for (int t = 0; t < 4; ++t) nt[rb][t] = qnorm(rb * 16 + 4 * kq + t) - 0x7FFFFFFF;
+    const int qn_own = qnorm(lane);  // |u|^2 of the row this lane keeps
     uint64_t top[KMAX];  // row row0 + lane, ascending
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) top[i] = KEY_EMPTY;
@@ -303,42 +302,43 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
             }
             const int jj = cb * 16 + col;
             const int64_t j = j0 + jj;
-            const int cn = cn_l[cur][jj];  // past the tile's end: too large to pass
+            const int ncn = -cn_l[cur][jj];  // past the tile's end: too small to pass
             bool any = false;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) any |= cn - 2 * acc[rb][t] <= tq[rb][t];
+                for (int t = 0; t < 4; ++t) any |= (acc[rb][t] << 1) + ncn >= nt[rb][t];
             if (__ballot(any) == 0) continue;
             // ---- slow path: survivors to their rows' buckets, owners merge
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int v = cn - 2 * acc[rb][t];
+                    const int wv = (acc[rb][t] << 1) + ncn;
                     const int wr = rb * 16 + 4 * kq + t;
                     const bool me = self_tile && j == row0 + wr;
-                    if (v <= tq[rb][t] && jj < tj && !me) {
+                    if (wv >= nt[rb][t] && jj < tj && !me) {
                         const int slot = atomicAdd(&bcnt[w][wr], 1);
-                        bucket[w][wr][slot] = make_key(uint32_t(v + qn[rb][t]), uint32_t(j));
+                        bucket[w][wr][slot] = make_key(uint32_t(wv), uint32_t(j));  // the owner adds |u|^2
                     }
                 }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
+            lds_wave_order();
             const int c = bcnt[w][lane];
-            for (int e = 0; e < c; ++e) topk_offer<KMAX>(top, bucket[w][lane][e]);
+            for (int e = 0; e < c; ++e) {
+                const uint64_t b = bucket[w][lane][e];
+                topk_offer<KMAX>(top, make_key(uint32_t(qn_own - int(key_dist(b))), key_id(b)));
+            }
             bcnt[w][lane] = 0;
             uint64_t th = top[0];
 #pragma unroll
             for (int i = 1; i < KMAX; ++i)
                 if (i == k - 1) th = top[i];
-            const int thr = th == KEY_EMPTY ? 0x7FFFFFFF : int(key_dist(th));
+            const int nthr = qn_own - (th == KEY_EMPTY ? 0x7FFFFFFF : int(key_dist(th)));
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-                for (int t = 0; t < 4; ++t) tq[rb][t] = __shfl(thr, rb * 16 + 4 * kq + t) - qn[rb][t];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-            __builtin_amdgcn_wave_barrier();
+                for (int t = 0; t < 4; ++t) nt[rb][t] = __shfl(nthr, rb * 16 + 4 * kq + t);
+            lds_wave_order();
         }
         if (more) stash(cur ^ 1);
         __syncthreads();
@@ -523,8 +523,7 @@ __global__ void __launch_bounds__(256) k_knn_mfma_f32(const float* X, const floa
                 }
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        lds_wave_order();
         float thr = __builtin_inff();
         if (lane < 16) {
             const int c = bcnt[w][lane];
@@ -538,8 +537,7 @@ __global__ void __launch_bounds__(256) k_knn_mfma_f32(const float* X, const floa
         }
 #pragma unroll
         for (int t = 0; t < 4; ++t) tq[t] = __shfl(thr, 4 * kq + t) - qn[t];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        lds_wave_order();
     }
     const int64_t qi = row0 + lane;
     if (lane >= 16 || qi >= nq) return;

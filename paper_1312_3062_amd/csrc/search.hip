@@ -389,13 +389,11 @@ __device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool
     const int po = lane + above, pn = old_below + new_below;
     if (old && po < cap) buf[po] = v;
     if (isnew && pn < cap) buf[pn] = x;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    lds_wave_order();
     const int total = min(cap, n + m);
     v = lane < total ? buf[lane] : KEY_EMPTY;
     n = total;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    lds_wave_order();
 }
 
 // remove and return the smallest key (n > 0)
