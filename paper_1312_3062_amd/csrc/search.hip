@@ -41,7 +41,7 @@ namespace {
 
 enum { MODE_U8 = 0, MODE_F32 = 1, MODE_BF16 = 2 };
 
-constexpr int GEN_BATCH = 32;  // bridges extracted per look-ahead step
+constexpr int GEN_BATCH = 32;  // most bridges extracted per refill (ring capacity above T = 2048)
 constexpr int MAX_SPEC = 8;    // references whose rows are loaded ahead together
 constexpr int PRE_LIST = 8;    // bridge lists up to this length are fetched with the bridge
 
@@ -70,6 +70,7 @@ struct SearchArgs {
     uint32_t dc_buckets;    // distance cache: buckets of 4 slots
     int spec;               // S, references loaded ahead (S * R <= 64)
     int ms_cap;             // multi-sequence: materialised side and outer frontier capacity
+    int gen_batch;          // ring capacity: most bridges extracted per refill
     int prefetch;           // fetch short bridge lists (and distances) with the bridges
     uint32_t* ovf_list;  // queries whose LDS heap overflowed
     uint32_t* ovf_count;
@@ -591,8 +592,11 @@ struct PairMSeq {
     }
 };
 
-template <int MODE, int NC16, int KPL, bool RERUN>
-__global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
+// COUNT: per-query counters and the evaluation trace are recorded (when the
+// caller asked for either); without them fewer scalars stay live.
+template <int MODE, int NC16, int KPL, bool RERUN, bool COUNT>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(KPL <= 2 ? 4 : 1, 8)))
+k_search(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr bool FLOAT = Traits<MODE>::FLOAT;
 
@@ -614,12 +618,6 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
     uint64_t* mrg = reinterpret_cast<uint64_t*>(lds + a.o_mrg);  // merge buffer, 64 keys
 
-    const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, a.K, a.P);
-    MSeqMem msm;
-    if constexpr (RERUN)
-        msm = mseq_carve(a.gheap + int64_t(blockIdx.x) * slot_bytes, a.gms_cap, a.K, a.P);
-    else
-        msm = mseq_carve(lds + a.o_ms, a.ms_cap, a.K, a.P);
 
     const int lane = lane_id();
     const int64_t n = a.n;
@@ -666,10 +664,23 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, H, sv, perm, lane);
         for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
         __syncthreads();
-        MSeqConf msc = mseq_conf(sv, perm, P, K, uint32_t(n), msm);
-        PairMSeq<FLOAT> ms;
-        if (lane == 0) ms.init(msc);
         int slot = -1;  // global slot the enumeration moved to (main kernel)
+        // where the enumeration state lives: LDS, or a global slot (the re-run
+        // kernel's workgroup b owns slot b); rebuilt where used rather than kept
+        // in registers across the search
+        auto ms_conf = [&]() {
+            const int64_t slot_bytes = mseq_slot_bytes(a.gms_cap, K, P);
+            MSeqMem m;
+            if (RERUN)
+                m = mseq_carve(a.gheap + int64_t(blockIdx.x) * slot_bytes, a.gms_cap, K, P);
+            else if (slot >= 0)
+                m = mseq_carve(a.gheap + int64_t(slot) * slot_bytes, a.gms_cap, K, P);
+            else
+                m = mseq_carve(lds + a.o_ms, a.ms_cap, K, P);
+            return mseq_conf(sv, perm, P, K, uint32_t(n), m);
+        };
+        PairMSeq<FLOAT> ms;
+        if (lane == 0) ms.init(ms_conf());
         bool ms_alive = true;  // the enumeration can still yield bridges
         int heap_max = 1;
         int flags = 0;
@@ -694,7 +705,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
         // the lanes with `ev` hold evaluated keys (rank r in adjacency order):
         // record them and offer them to the result set and the main queue
         auto offer = [&](uint64_t key, bool ev) {
-            if (a.trace && ev) a.trace[qi * a.Tall + t + r] = int32_t(key_id(key));
+            if (COUNT && a.trace && ev) a.trace[qi * a.Tall + t + r] = int32_t(key_id(key));
             const uint64_t rworst = rn < rcap ? KEY_EMPTY : reg_get<KPL>(Rv, rn - 1);
             const bool ra = ev && key < rworst;
             if (__ballot(ra)) {
@@ -718,7 +729,8 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     if (lane == 0) {
                         // batches of 4, 8, 16, then 32 bridges: at small budgets a
                         // query expands about one bridge
-                        const int gb = min(GEN_BATCH, 4 << min(refills, 3));
+                        const int gb = min(a.gen_batch, 4 << min(refills, 3));
+                        const MSeqConf msc = ms_conf();
                         int g = 0;
                         uint64_t key;
                         bool move = false;
@@ -739,10 +751,10 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     __syncthreads();
                     const bool move = sc[5] != 0;
                     ms_alive = sc[0] != 0;
-                    heap_max = sc[4];
+                    if constexpr (COUNT) heap_max = sc[4];
                     const int g = sc[2];
                     if (sc[1]) flags = ANN_ERESOURCE;
-                    st_gen += g;
+                    if constexpr (COUNT) st_gen += g;
                     bool ne = false;
                     uint64_t key = 0;
                     uint32_t o0 = 0, o1 = 0;
@@ -797,7 +809,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                                     need = true;
                             }
                             const uint32_t gdist = gather_need<MODE, NC16>(a, qv, pid, need, gid, gd, lane);
-                            st_rows += __popcll(__ballot(need));
+                            if constexpr (COUNT) st_rows += __popcll(__ballot(need));
                             pre_d[sl] = need ? gdist : d;
                         }
                     }
@@ -830,12 +842,13 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                                 sc[11] = ms.hon;
                             }
                             __syncthreads();
-                            slot = sc[6];
-                            if (slot < 0) {
+                            const int got = sc[6];
+                            if (got < 0) {
                                 flags = ANN_ERESOURCE;
                             } else {
-                                const MSeqMem g = mseq_carve(a.gheap + int64_t(slot) * slot_bytes, a.gms_cap, K, P);
-                                const MSeqMem l = msc.m;
+                                const MSeqMem l = ms_conf().m;  // the LDS state (no slot yet)
+                                slot = got;
+                                const MSeqMem g = ms_conf().m;
                                 for (int i = lane; i < sc[7]; i += WAVE) g.mx[i] = l.mx[i];
                                 for (int i = lane; i < sc[8]; i += WAVE) g.my[i] = l.my[i];
                                 for (int i = lane; i < sc[9]; i += WAVE) {
@@ -850,7 +863,6 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                                     g.hok[i] = l.hok[i];
                                     g.hor[i] = l.hor[i];
                                 }
-                                msc.m = g;
                             }
                             __syncthreads();
                         }
@@ -879,7 +891,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                 if (!hit) {
                     // work ahead: rows of the S best queue entries, distances of
                     // their unvisited neighbours not yet in the cache
-                    ++st_spec;
+                    if constexpr (COUNT) ++st_spec;
                     if (dc_fill > dc_limit) {
                         for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
                         dc_fill = 0;
@@ -909,14 +921,14 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     if (need) DV[slot] = gdist;
                     const int m = __popcll(__ballot(need));
                     dc_fill += m;
-                    st_rows += m;
+                    if constexpr (COUNT) st_rows += m;
                     __syncthreads();
                     ac_d = known ? (need ? gdist : DV[slot]) : 0u;
                     hit = 1;  // entry 0 is the queue head
                 }
                 const int s = __builtin_ctzll(hit);
                 reg_pop_front(Qv, qn);
-                ++st_rpop;
+                if constexpr (COUNT) ++st_rpop;
                 // ---- expand: the row sits in lanes [s*R, s*R + R)
                 const bool inrow = R > 0 && row_lane_slot == s && lane < (s + 1) * R;
                 bool white = false;
@@ -933,8 +945,10 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                 const int len = int(ring_len[e]);
                 ++ring_h;
                 bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
-                ++st_bpop;
-                st_bids += len;
+                if constexpr (COUNT) {
+                    ++st_bpop;
+                    st_bids += len;
+                }
                 id = lane < len ? pre_id[e * PRE_LIST + lane] : ID_EMPTY;
                 bool white = false;
                 if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
@@ -948,7 +962,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
                     const bool miss = ev && slot < 0;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
-                    st_rows += __popcll(__ballot(miss));
+                    if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
                     dist = slot >= 0 ? DV[slot] : gdist;
                 }
             } else {
@@ -957,8 +971,10 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                 const int len = int(ring_len[ring_h]);
                 ++ring_h;
                 bkey = ring_h < ring_n ? ring_key[ring_h] : KEY_EMPTY;
-                ++st_bpop;
-                st_bids += len;
+                if constexpr (COUNT) {
+                    ++st_bpop;
+                    st_bids += len;
+                }
                 // lists longer than a wave are walked in chunks; every chunk but
                 // the one that ends the list or the budget is merged here, that
                 // one below
@@ -974,7 +990,7 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                     const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
                     const bool miss = ev && slot < 0;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
-                    st_rows += __popcll(__ballot(miss));
+                    if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
                     dist = slot >= 0 ? DV[slot] : gdist;
                     if (c0 + WAVE >= len || t + take >= T) break;
                     offer(make_key(dist, id), ev);
@@ -1061,9 +1077,9 @@ __global__ void __launch_bounds__(WAVE) k_search(SearchArgs a) {
                 }
             }
         }
-        if (a.trace)
+        if (COUNT && a.trace)
             for (int i = t + lane; i < a.Tall; i += WAVE) a.trace[qi * a.Tall + i] = -1;
-        if (a.stats && lane == 0) {
+        if (COUNT && a.stats && lane == 0) {
             int32_t* s = a.stats + qi * ANN_NSTATS;
             s[ANN_STAT_EVALS] = t;
             s[ANN_STAT_REF_POPS] = st_rpop;
@@ -1155,9 +1171,9 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
     a.o_sv = take(PK * 4, 8);
     a.o_perm = take(PK, 8);
     a.o_ms = with_heap ? take(mseq_bytes(a.ms_cap, a.K, a.P), 16) : 0;
-    a.o_rk = take(GEN_BATCH * 8, 8);
-    a.o_ro = take(GEN_BATCH * 4, 8);
-    a.o_rl = take(GEN_BATCH * 4, 8);
+    a.o_rk = take(a.gen_batch * 8, 8);
+    a.o_ro = take(a.gen_batch * 4, 8);
+    a.o_rl = take(a.gen_batch * 4, 8);
     a.o_sk = a.o_rk;  // a batch is staged where it is compacted into the ring
     a.o_pid = a.prefetch ? take(GEN_BATCH * PRE_LIST * 4, 16) : 0;
     a.o_pd = a.prefetch ? take(GEN_BATCH * PRE_LIST * 4, 16) : 0;
@@ -1180,10 +1196,9 @@ struct Grid {
     int cus;
 };
 
-template <int MODE, int NC16, int KPL>
-int launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, Grid g, int grid2,
-                hipStream_t st) {
-    auto* k1 = k_search<MODE, NC16, KPL, false>;
+template <int MODE, int NC16, int KPL, bool COUNT>
+int launch_mode_c(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, Grid g, int grid2, hipStream_t st) {
+    auto* k1 = k_search<MODE, NC16, KPL, false, COUNT>;
     int64_t grid = g.grid;
     if (a1.work_counter) {
         int per_cu = 0;
@@ -1193,8 +1208,15 @@ int launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, 
         grid = std::min<int64_t>(a1.nq, int64_t(per_cu) * g.cus);
     }
     hipLaunchKernelGGL(k1, dim3(unsigned(grid)), dim3(WAVE), lds1, st, a1);
-    hipLaunchKernelGGL((k_search<MODE, NC16, KPL, true>), dim3(unsigned(grid2)), dim3(WAVE), lds2, st, a2);
+    hipLaunchKernelGGL((k_search<MODE, NC16, KPL, true, COUNT>), dim3(unsigned(grid2)), dim3(WAVE), lds2, st, a2);
     return ANN_OK;
+}
+
+template <int MODE, int NC16, int KPL>
+int launch_mode(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2, Grid g, int grid2,
+                hipStream_t st) {
+    if (a1.stats || a1.trace) return launch_mode_c<MODE, NC16, KPL, true>(a1, a2, lds1, lds2, g, grid2, st);
+    return launch_mode_c<MODE, NC16, KPL, false>(a1, a2, lds1, lds2, g, grid2, st);
 }
 
 template <int MODE, int NC16>
@@ -1272,10 +1294,10 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.trace = s.d_trace;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates); buckets for a final load of about 0.8.  The
+    // than it evaluates); buckets for a final load of about 0.85.  The
     // distance cache (cleared when half full) gets at least 64 buckets and
     // grows into the slack of the last LDS granule (below).
-    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
+    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 20 / 17 / 4 + 1));
     a.dc_buckets = 64;
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
@@ -1285,8 +1307,9 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // all the work (one bridge per query on the 1M workload); beyond it
     // bridges take over and their lists are fetched ahead.
     const int64_t side = int64_t(idx->K) * idx->K;
-    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 16)) : int(std::min<int64_t>(side, 256));
+    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 8)) : int(std::min<int64_t>(side, 256));
     a.prefetch = s.Tmax > 2048 ? 1 : 0;
+    a.gen_batch = s.Tmax <= 2048 ? 16 : GEN_BATCH;
 
     const int qbytes = pl.is_f32 ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
