@@ -52,9 +52,10 @@ def gt_f32(X, xd, Q, k, torch, knn_device, cand=32):
     return out
 
 
-def precision_leg(idx, w, X, Q, gt, T, torch):
-    """fp32 search vs bf16 gather with fp32 re-rank on the same queries: recall@k
-    and the error of returned and candidate distances against fp64."""
+def precision_leg(idx, w, X, Q, gt, T, torch, steps=10):
+    """fp32 search vs bf16 gather with fp32 re-rank on the same queries: recall@k,
+    queries/s (kernel time, HIP events) and the error of returned and candidate
+    distances against fp64."""
     from paper_1312_3062_amd import recall_at
     qd = torch.from_numpy(Q).cuda()
     res = {}
@@ -63,10 +64,18 @@ def precision_leg(idx, w, X, Q, gt, T, torch):
     for name, prec, rr in (("fp32", 0, 0), ("bf16_rerank", 1, 4 * w.k)):
         ids, dd = idx.search_device(qd, w.k, T, queue_len=w.queue_len, precision=prec, rerank_k=rr)
         torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in ev:
+            a.record()
+            idx.search_device(qd, w.k, T, queue_len=w.queue_len, precision=prec, rerank_k=rr)
+            b.record()
+        torch.cuda.synchronize()
+        kms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
         ids, dd = ids.cpu().numpy(), dd.cpu().numpy().astype(np.float64)
         ex = ((Xd[ids] - Qd[:, None, :]) ** 2).sum(2)
         rel = np.abs(dd - ex) / np.maximum(ex, 1e-30)
         res[name] = {"recall@10": round(recall_at(ids, gt, w.k), 4), "rerank_k": rr or None,
+                     "kernel_ms": round(kms, 3), "qps": round(len(Q) / (kms * 1e-3), 1),
                      "max_rel_err_returned": float(f"{rel.max():.3g}"),
                      "mean_rel_err_returned": float(f"{rel.mean():.3g}")}
     # the bf16 approximation the traversal runs on, for the fp32 results' ids

@@ -216,13 +216,64 @@ __device__ inline uint32_t group_sum(uint32_t v, int lpr) {
     }
 }
 
+// Float rows of a size fixed at compile time (NC16 16-byte chunks): 8 lanes
+// per row, every chunk of a lane (chunks part, part + 8, ...) loaded before
+// any is used, so a pass over 8 rows is one memory round trip.
+constexpr int FIXED_LPR = 8;
+
+template <int MODE, int NC16>
+__device__ inline uint32_t row_partial_fixed(const uint8_t* row, const uint8_t* qv, int part) {
+    constexpr int CPL = NC16 / FIXED_LPR;
+    float acc = 0.f;
+    if constexpr (MODE == MODE_F32) {
+        float4 x[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) x[u] = reinterpret_cast<const float4*>(row)[part + u * FIXED_LPR];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const float4 q = reinterpret_cast<const float4*>(qv)[part + u * FIXED_LPR];
+            float t0 = q.x - x[u].x, t1 = q.y - x[u].y, t2 = q.z - x[u].z, t3 = q.w - x[u].w;
+            acc = fmaf(t0, t0, acc);
+            acc = fmaf(t1, t1, acc);
+            acc = fmaf(t2, t2, acc);
+            acc = fmaf(t3, t3, acc);
+        }
+    } else {
+        uint4 x[CPL];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) x[u] = reinterpret_cast<const uint4*>(row)[part + u * FIXED_LPR];
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = part + u * FIXED_LPR;  // bf16 dims [8c, 8c + 8); the query stays fp32
+            const float4 qa = *reinterpret_cast<const float4*>(qv + c * 32);
+            const float4 qb = *reinterpret_cast<const float4*>(qv + c * 32 + 16);
+            float t;
+            t = qa.x - bf16_lo(x[u].x); acc = fmaf(t, t, acc);
+            t = qa.y - bf16_hi(x[u].x); acc = fmaf(t, t, acc);
+            t = qa.z - bf16_lo(x[u].y); acc = fmaf(t, t, acc);
+            t = qa.w - bf16_hi(x[u].y); acc = fmaf(t, t, acc);
+            t = qb.x - bf16_lo(x[u].z); acc = fmaf(t, t, acc);
+            t = qb.y - bf16_hi(x[u].z); acc = fmaf(t, t, acc);
+            t = qb.z - bf16_lo(x[u].w); acc = fmaf(t, t, acc);
+            t = qb.w - bf16_hi(x[u].w); acc = fmaf(t, t, acc);
+        }
+    }
+    return f_bits(acc);
+}
+
+// lanes that share a gathered row
+template <int MODE, int NC16>
+__host__ __device__ constexpr int gather_lpr() {
+    return Traits<MODE>::LPR == 1 ? 1 : (NC16 > 0 ? FIXED_LPR : Traits<MODE>::LPR);
+}
+
 // Distance of the row `id` for every lane with `need`, returned in that lane.
 // One lane per row (u8); otherwise the rows are listed in LDS and groups of
 // LPR lanes gather them, RPP rows per pass.
 template <int MODE, int NC16>
 __device__ inline uint32_t gather_need(const SearchArgs& a, const uint8_t* qv, uint32_t id, bool need, uint32_t* gid,
                                        uint32_t* gd, int lane) {
-    constexpr int LPR = Traits<MODE>::LPR;
+    constexpr int LPR = gather_lpr<MODE, NC16>();
     if constexpr (LPR == 1) {
         uint32_t d = 0;
         if (need) d = row_partial<MODE, NC16>(a.X + int64_t(id) * a.row_bytes, qv, int(a.row_bytes / 16), 0, 1);
@@ -239,7 +290,13 @@ __device__ inline uint32_t gather_need(const SearchArgs& a, const uint8_t* qv, u
         for (int p0 = 0; p0 < m; p0 += RPP) {
             const int row = p0 + grp;
             uint32_t ps = 0;
-            if (row < m) ps = row_partial<MODE, 0>(a.X + int64_t(gid[row]) * a.row_bytes, qv, nc16, part, LPR);
+            if (row < m) {
+                const uint8_t* src = a.X + int64_t(gid[row]) * a.row_bytes;
+                if constexpr (NC16 > 0)
+                    ps = row_partial_fixed<MODE, NC16>(src, qv, part);
+                else
+                    ps = row_partial<MODE, 0>(src, qv, nc16, part, LPR);
+            }
             const uint32_t dsum = group_sum<MODE>(ps, LPR);
             if (part == 0 && row < m) gd[row] = dsum;
         }
@@ -595,7 +652,7 @@ struct PairMSeq {
 // COUNT: per-query counters and the evaluation trace are recorded (when the
 // caller asked for either); without them fewer scalars stay live.
 template <int MODE, int NC16, int KPL, bool RERUN, bool COUNT>
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(KPL <= 2 ? 4 : 1, 8)))
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(MODE == MODE_U8 && KPL <= 2 ? 4 : 1, 8)))
 k_search(SearchArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     constexpr bool FLOAT = Traits<MODE>::FLOAT;
@@ -1307,7 +1364,13 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // all the work (one bridge per query on the 1M workload); beyond it
     // bridges take over and their lists are fetched ahead.
     const int64_t side = int64_t(idx->K) * idx->K;
-    a.ms_cap = s.Tmax <= 2048 ? int(std::min<int64_t>(side, 8)) : int(std::min<int64_t>(side, 256));
+    // The state is only fast in LDS: a query that outgrows it continues at L2
+    // latency, one lane at a time.  With four lists of at most 64 codewords
+    // a query at T <= 2048 expands about one bridge and 8 elements per side
+    // suffice; with three lists or K >= 100 (fewer, larger sides, more
+    // bridges expanded) the state gets 256.
+    const bool few_bridges = idx->P >= 4 && idx->K <= 64;
+    a.ms_cap = int(std::min<int64_t>(side, s.Tmax <= 2048 && few_bridges ? 8 : 256));
     a.prefetch = s.Tmax > 2048 ? 1 : 0;
     a.gen_batch = s.Tmax <= 2048 ? 16 : GEN_BATCH;
 
@@ -1484,9 +1547,15 @@ int launch_search(const SearchLaunch& s) {
             else
                 rc = launch_kpl<MODE_U8, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
         } else if (pl.bf16) {
-            rc = launch_kpl<MODE_BF16, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+            if (idx->d == 384)
+                rc = launch_kpl<MODE_BF16, 48>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+            else
+                rc = launch_kpl<MODE_BF16, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
         } else {
-            rc = launch_kpl<MODE_F32, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+            if (idx->d == 384)
+                rc = launch_kpl<MODE_F32, 96>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
+            else
+                rc = launch_kpl<MODE_F32, 0>(pl.rcap, a, a2, pl.lds1, pl.lds2, g, pl.grid2, s.stream);
         }
         if (rc) return rc;
         ANN_HIP_CHECK(hipGetLastError());
