@@ -351,3 +351,22 @@ def test_multisequence_overflow_without_a_free_slot_is_rerun_exactly():
                            k, T, 64)
     np.testing.assert_array_equal(ids.cpu().numpy(), oi)
     np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
+
+
+# ---------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("k,T", [(129, 700), (500, 900), (1024, 1500)])
+def test_large_k_bit_exact(tiny, k, T):
+    """Result sets beyond 128 keys (16 per lane), up to the 1024 maximum."""
+    Q = tiny["Q"][:12]
+    assert_search_equal(tiny["idx"], tiny["parts"], tiny["X"], Q, k, T, 64)
+
+
+def test_empty_batch_and_zero_budget(tiny):
+    idx = tiny["idx"]
+    qd = torch.empty((0, tiny["X"].shape[1]), dtype=torch.uint8, device="cuda")
+    ids, dd = idx.search_device(qd, 10, 256)
+    torch.cuda.synchronize()
+    assert ids.shape == (0, 10) and dd.shape == (0, 10)
+    gi, gd = gpu_search(idx, tiny["Q"][:5], 7, 0, 64)
+    assert (gi == -1).all() and (gd == 2147483647).all()
