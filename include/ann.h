@@ -48,7 +48,7 @@ typedef enum {
     ANN_ENOMEM = -2,       /* device or host allocation failed */
     ANN_EDEVICE = -3,      /* a HIP call failed */
     ANN_ESTATE = -4,       /* object in the wrong state */
-    ANN_EUNSUPPORTED = -5, /* valid request outside what this build implements */
+    ANN_EUNSUPPORTED = -5, /* valid request outside what the library implements */
     ANN_EIO = -6,          /* file could not be read or written */
     ANN_ERESOURCE = -7     /* a per-query structure outgrew its capacity */
 } ann_status;
