@@ -455,6 +455,7 @@ int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq
     if (rc) return rc;
     ANN_REQUIRE(nq == 0 || (d_queries && d_ids && d_dists), "search: null device buffer");
     ANN_REQUIRE(nq == 0 || workspace, "ann_search_device_ws: null workspace");
+    ANN_REQUIRE((reinterpret_cast<uintptr_t>(workspace) & 15) == 0, "ann_search_device_ws: workspace not 16-byte aligned");
     SearchLaunch a =
         make_launch(idx, d_queries, nq, k, budget, d_k, d_budget, sp, d_ids, d_dists, d_stats, d_trace, stream);
     a.workspace = workspace;

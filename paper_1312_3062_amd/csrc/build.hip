@@ -192,13 +192,12 @@ __global__ void k_kmeans_update(void* cb, const uint64_t* sums, const uint32_t* 
 // multi-sequence heap.  One wavefront per reference vector.
 // Output key = (distance bits << 32 | reference id), lid alongside.
 // ----------------------------------------------------------------------
-__host__ __device__ inline int topt_layout(int rowb, int PK, int heap_cap, int& o_tab, int& o_sv, int& o_hk,
-                                           int& o_hr, int& o_perm) {
+__host__ __device__ inline int topt_layout(int rowb, int PK, int heap_cap, int& o_tab, int& o_sv, int& o_heap,
+                                           int& o_perm) {
     o_tab = (rowb + 15) & ~15;
     o_sv = o_tab + PK * 4;
-    o_hk = (o_sv + PK * 4 + 7) & ~7;
-    o_hr = o_hk + heap_cap * 8;
-    o_perm = o_hr + heap_cap * 4;
+    o_heap = (o_sv + PK * 4 + 15) & ~15;
+    o_perm = o_heap + heap_cap * int(sizeof(hent_t));
     return (o_perm + PK + 15) & ~15;
 }
 
@@ -210,13 +209,12 @@ __global__ void __launch_bounds__(WAVE) k_bridge_topt(const uint8_t* X, int64_t 
     const int ds = d / P;
     const int PK = P * K;
     const int rowb = FLOAT ? d * 4 : d;
-    int o_tab, o_sv, o_hk, o_hr, o_perm;
-    topt_layout(rowb, PK, heap_cap, o_tab, o_sv, o_hk, o_hr, o_perm);
+    int o_tab, o_sv, o_heap, o_perm;
+    topt_layout(rowb, PK, heap_cap, o_tab, o_sv, o_heap, o_perm);
     uint8_t* qv = lds;
     uint32_t* tab = reinterpret_cast<uint32_t*>(lds + o_tab);
     uint32_t* sv = reinterpret_cast<uint32_t*>(lds + o_sv);
-    uint64_t* hk = reinterpret_cast<uint64_t*>(lds + o_hk);
-    uint32_t* hr = reinterpret_cast<uint32_t*>(lds + o_hr);
+    hent_t* heap = reinterpret_cast<hent_t*>(lds + o_heap);
     uint8_t* perm = lds + o_perm;
     const int lane = lane_id();
     for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -227,11 +225,11 @@ __global__ void __launch_bounds__(WAVE) k_bridge_topt(const uint8_t* X, int64_t 
         if (lane == 0) {
             // keys carry n + lid like the search; strip n when writing
             int hn = 0;
-            heap_push(hk, hr, hn, tuple_key<FLOAT>(0u, sv, perm, P, K, 0), 0u);
+            heap_push(heap, hn, tuple_key<FLOAT>(0u, sv, perm, P, K, 0), 0u);
             for (int j = 0; j < t; ++j) {
                 uint64_t key;
                 uint32_t rk;
-                heap_pop(hk, hr, hn, key, rk);
+                heap_pop(heap, hn, key, rk);
                 out_lid[i * t + j] = key_id(key);
                 out_key[i * t + j] = make_key(key_dist(key), uint32_t(i));
                 atomicAdd(&counts[key_id(key)], 1u);
@@ -242,7 +240,7 @@ __global__ void __launch_bounds__(WAVE) k_bridge_topt(const uint8_t* X, int64_t 
                     const int r = (rk >> (8 * b)) & 0xFF;
                     if (r + 1 >= K) continue;
                     const uint32_t crk = rk + (1u << (8 * b));
-                    heap_push(hk, hr, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, 0), crk);
+                    heap_push(heap, hn, tuple_key<FLOAT>(crk, sv, perm, P, K, 0), crk);
                 }
             }
         }
@@ -432,8 +430,8 @@ int build_bridge_graph(ann_index* idx, int t, int b, hipStream_t s) {
     const int heap_cap = 1 + (idx->P - 1) * t + idx->P;
     const int rowb = f ? idx->d * 4 : idx->d;
     const int PK = idx->P * idx->K;
-    int o1, o2, o3, o4, o5;
-    const int lds = topt_layout(rowb, PK, heap_cap, o1, o2, o3, o4, o5);
+    int o1, o2, o3, o4;
+    const int lds = topt_layout(rowb, PK, heap_cap, o1, o2, o3, o4);
     int dev = 0, max_lds = 0;
     ANN_HIP_CHECK(hipGetDevice(&dev));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

@@ -1,6 +1,6 @@
 // Device code shared by the search and the bridge-graph build: subspace
 // distance tables with their per-subspace sort (Sec. 4.2) and the
-// multi-sequence frontier (Sec. 3.3), a binary min-heap of bridge keys.
+// multi-sequence frontier (Sec. 3.3), a 4-ary min-heap of bridge keys.
 #pragma once
 
 #include "common.hpp"
@@ -50,8 +50,8 @@ __device__ inline void compute_tables(const uint8_t* qv, const void* cb, int P, 
 }
 
 // ------------------------------------------------------------------
-// multi-sequence frontier: binary min-heap of (sum << 32 | n + lid) keys
-// with the packed rank tuple (8 bits per subspace) alongside
+// multi-sequence frontier: min-heap of (sum << 32 | n + lid) keys with the
+// packed rank tuple (8 bits per subspace) alongside
 // ------------------------------------------------------------------
 template <bool FLOAT>
 __device__ inline uint64_t tuple_key(uint32_t rk, const uint32_t* sv, const uint8_t* perm, int P, int K, int64_t n) {
@@ -70,45 +70,68 @@ __device__ inline uint64_t tuple_key(uint32_t rk, const uint32_t* sv, const uint
     return make_key(FLOAT ? f_bits(fs) : s, uint32_t(n) + lid);
 }
 
-__device__ inline void heap_push(uint64_t* hk, uint32_t* hr, int& hn, uint64_t key, uint32_t rk) {
-    int i = hn++;
-    while (i > 0) {
-        const int par = (i - 1) >> 1;
-        const uint64_t pk = hk[par];
-        if (pk <= key) break;
-        hk[i] = pk;
-        hr[i] = hr[par];
-        i = par;
-    }
-    hk[i] = key;
-    hr[i] = rk;
+// A frontier entry: key (low, high word) and packed ranks side by side in
+// one 16-byte vector, so that one access moves both.
+typedef uint32_t hent_t __attribute__((ext_vector_type(4)));
+__device__ inline uint64_t hkey(hent_t e) { return (uint64_t(e.y) << 32) | e.x; }
+__device__ inline hent_t hmake(uint64_t key, uint32_t rk) {
+    hent_t e;
+    e.x = uint32_t(key);
+    e.y = uint32_t(key >> 32);
+    e.z = rk;
+    e.w = 0u;
+    return e;
 }
 
-__device__ inline void heap_pop(uint64_t* hk, uint32_t* hr, int& hn, uint64_t& key, uint32_t& rk) {
-    key = hk[0];
-    rk = hr[0];
+// 4-ary min-heap: half the levels of a binary heap, and the four children of
+// a node are read together, so a level costs one memory round trip.  Keys
+// are distinct, so the order of extraction is the keys' order whatever the
+// heap's shape.  HP is a pointer to hent_t in any address space (LDS, global
+// or generic).
+template <typename HP>
+__device__ inline void heap_push(HP h, int& hn, uint64_t key, uint32_t rk) {
+    int i = hn++;
+    while (i > 0) {
+        const int par = (i - 1) >> 2;
+        const hent_t pe = h[par];
+        if (hkey(pe) <= key) break;
+        h[i] = pe;
+        i = par;
+    }
+    h[i] = hmake(key, rk);
+}
+
+template <typename HP>
+__device__ inline void heap_pop(HP h, int& hn, uint64_t& key, uint32_t& rk) {
+    const hent_t top = h[0];
+    key = hkey(top);
+    rk = top.z;
     --hn;
-    const uint64_t lk = hk[hn];
-    const uint32_t lr = hr[hn];
+    const hent_t last = h[hn];
+    const uint64_t lk = hkey(last);
     int i = 0;
     for (;;) {
-        int c = 2 * i + 1;
+        const int c = 4 * i + 1;
         if (c >= hn) break;
-        uint64_t ck = hk[c];
-        if (c + 1 < hn) {
-            const uint64_t ck2 = hk[c + 1];
-            if (ck2 < ck) {
-                ck = ck2;
-                ++c;
+        // children past the end are read at a valid index and ignored; the
+        // ranks are read with the keys (one round trip), not after the choice
+        hent_t e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = h[min(c + q, hn - 1)];
+        asm volatile("" ::"v"(e[0].z), "v"(e[1].z), "v"(e[2].z), "v"(e[3].z));
+        int bc = c;
+        hent_t b = e[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (c + q < hn && hkey(e[q]) < hkey(b)) {
+                b = e[q];
+                bc = c + q;
             }
-        }
-        if (lk <= ck) break;
-        hk[i] = ck;
-        hr[i] = hr[c];
-        i = c;
+        if (lk <= hkey(b)) break;
+        h[i] = b;
+        i = bc;
     }
-    hk[i] = lk;
-    hr[i] = lr;
+    h[i] = last;
 }
 
 }  // namespace ann

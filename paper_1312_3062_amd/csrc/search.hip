@@ -112,14 +112,24 @@ struct Traits<MODE_BF16> {
 template <int MODE, int NC16>
 __device__ inline uint32_t row_partial(const uint8_t* row, const uint8_t* qv, int nc16, int part, int lpr);
 
-template <>
-__device__ inline uint32_t row_partial<MODE_U8, 8>(const uint8_t* row, const uint8_t* qv, int, int, int) {
-    // d = 128: the whole 128-byte row in one lane, all loads in flight at once.
-    // sum (q-x)^2 = sum q^2 + sum x^2 - 2 sum q*x, every term an exact integer
+// sum of squares of the query's bytes (u8 rows of 128 bytes take it precomputed)
+__device__ inline uint32_t query_norm_u8(const uint8_t* qv, int d) {
+    uint32_t qq = 0;
+    for (int c = 0; c < d / 4; ++c) {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(qv)[c];
+        qq = __builtin_amdgcn_udot4(w, w, qq, false);
+    }
+    return qq;
+}
+
+// d = 128: the whole 128-byte row in one lane, all loads in flight at once.
+// sum (q-x)^2 = sum q^2 + sum x^2 - 2 sum q*x, every term an exact integer;
+// qq = sum q^2 is the query's, computed once
+__device__ inline uint32_t row_dist_u8_128(const uint8_t* row, const uint8_t* qv, uint32_t qq) {
     uint4 x[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) x[c] = reinterpret_cast<const uint4*>(row)[c];
-    uint32_t xx = 0, qq = 0, qx = 0;
+    uint32_t xx = 0, qx = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const uint4 q = *reinterpret_cast<const uint4*>(qv + c * 16);
@@ -127,10 +137,6 @@ __device__ inline uint32_t row_partial<MODE_U8, 8>(const uint8_t* row, const uin
         xx = __builtin_amdgcn_udot4(x[c].y, x[c].y, xx, false);
         xx = __builtin_amdgcn_udot4(x[c].z, x[c].z, xx, false);
         xx = __builtin_amdgcn_udot4(x[c].w, x[c].w, xx, false);
-        qq = __builtin_amdgcn_udot4(q.x, q.x, qq, false);
-        qq = __builtin_amdgcn_udot4(q.y, q.y, qq, false);
-        qq = __builtin_amdgcn_udot4(q.z, q.z, qq, false);
-        qq = __builtin_amdgcn_udot4(q.w, q.w, qq, false);
         qx = __builtin_amdgcn_udot4(q.x, x[c].x, qx, false);
         qx = __builtin_amdgcn_udot4(q.y, x[c].y, qx, false);
         qx = __builtin_amdgcn_udot4(q.z, x[c].z, qx, false);
@@ -271,12 +277,17 @@ __host__ __device__ constexpr int gather_lpr() {
 // One lane per row (u8); otherwise the rows are listed in LDS and groups of
 // LPR lanes gather them, RPP rows per pass.
 template <int MODE, int NC16>
-__device__ inline uint32_t gather_need(const SearchArgs& a, const uint8_t* qv, uint32_t id, bool need, uint32_t* gid,
-                                       uint32_t* gd, int lane) {
+__device__ inline uint32_t gather_need(const SearchArgs& a, const uint8_t* qv, uint32_t qq, uint32_t id, bool need,
+                                       uint32_t* gid, uint32_t* gd, int lane) {
     constexpr int LPR = gather_lpr<MODE, NC16>();
     if constexpr (LPR == 1) {
         uint32_t d = 0;
-        if (need) d = row_partial<MODE, NC16>(a.X + int64_t(id) * a.row_bytes, qv, int(a.row_bytes / 16), 0, 1);
+        if (need) {
+            if constexpr (MODE == MODE_U8 && NC16 == 8)
+                d = row_dist_u8_128(a.X + int64_t(id) * a.row_bytes, qv, qq);
+            else
+                d = row_partial<MODE, NC16>(a.X + int64_t(id) * a.row_bytes, qv, int(a.row_bytes / 16), 0, 1);
+        }
         return d;
     } else {
         constexpr int RPP = WAVE / LPR;
@@ -393,6 +404,14 @@ __device__ inline uint64_t wave_shl1(uint64_t v, uint64_t fill) {
     return (uint64_t(hi) << 32) | lo;
 }
 
+// v with lane l replaced by the wave-uniform value x (v_writelane_b32; the
+// lane select goes through m0, as two scalar operands would exceed the
+// constant bus)
+__device__ inline int write_lane(int v, int x, int l) {
+    asm("s_mov_b32 m0, %2\n\ts_nop 0\n\tv_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(x), "s"(l) : "m0");
+    return v;
+}
+
 // Offer the keys of the lanes with `isnew` (distinct, none present) to the
 // sorted array v[0..n) of capacity cap: each one goes to its rank and the
 // tail moves up one place; at capacity the largest key falls off.  Same
@@ -431,6 +450,9 @@ __device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool
     uint64_t nm = __ballot(isnew);
     const int m = __popcll(nm);
     const bool old = lane < n;
+    // lanes at or past n hold KEY_EMPTY, above every key offered, so the
+    // counts below need no mask of old lanes: the number of old keys below
+    // x_j is 64 minus the lanes whose key lies above x_j
     int above = 0;      // old key: new keys below it
     int new_below = 0;  // new key: new keys below it
     int old_below = 0;  // new key: old keys below it
@@ -438,11 +460,10 @@ __device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool
         const int j = __builtin_ctzll(nm);
         nm &= nm - 1;
         const uint64_t xj = readlane64(x, j);
-        const bool lt = old && xj < v;
-        above += lt;
-        new_below += isnew && xj < x;
-        const int ob = n - __popcll(__ballot(lt));  // keys are distinct
-        old_below = lane == j ? ob : old_below;
+        above += xj < v ? 1 : 0;
+        new_below += xj < x ? 1 : 0;
+        const int ob = WAVE - __popcll(__ballot(xj < v));  // keys are distinct
+        old_below = write_lane(old_below, ob, j);
     }
     const int po = lane + above, pn = old_below + new_below;
     if (old && po < cap) buf[po] = v;
@@ -477,17 +498,15 @@ __device__ inline uint64_t reg_pop_front(uint64_t (&v)[1], int& n) {
 // bridges extracted, not with their number.
 // ------------------------------------------------------------------
 struct MSeqMem {
-    uint64_t* mx;   // materialised X elements: sum << 32 | lid
-    uint64_t* my;   // materialised Y elements
-    uint64_t* hxk;  // inner heap of X: keys, ranks (ra << 8 | rb)
-    uint32_t* hxr;
-    uint64_t* hyk;  // inner heap of Y
-    uint32_t* hyr;
-    uint64_t* hok;  // outer heap: keys sum << 32 | n + lid, positions i << 16 | j
-    uint32_t* hor;
-    int cap;        // capacity of mx and my
-    int ocap;       // of the outer heap
+    uint64_t* mx;  // materialised X elements: sum << 32 | lid
+    uint64_t* my;  // materialised Y elements
+    hent_t* ho;    // outer heap: keys sum << 32 | n + lid, positions i << 16 | j
+    hent_t* hx;    // inner heap of X: keys, ranks ra << 8 | rb
+    hent_t* hy;    // inner heap of Y
+    int cap;       // capacity of mx and my
+    int ocap;      // of the outer heap
 };
+
 
 // Capacities.  A frontier holds at most one entry per started row, and a row
 // is started only once the element heading it is known: the outer frontier
@@ -506,7 +525,7 @@ __host__ __device__ inline MSeqCaps mseq_caps(int cap, int K, int P) {
 
 __host__ __device__ inline int mseq_bytes(int cap, int K, int P) {
     const MSeqCaps c = mseq_caps(cap, K, P);
-    return c.cap * 8 * 2 + c.ocap * 12 + c.icap * 12 * 2 + 64;
+    return c.cap * 8 * 2 + (c.ocap + c.icap * 2) * int(sizeof(hent_t)) + 64;
 }
 
 // a global slot: mseq_bytes rounded up so that every slot starts 64-byte aligned
@@ -515,14 +534,11 @@ __host__ __device__ inline int mseq_slot_bytes(int cap, int K, int P) { return (
 __device__ inline MSeqMem mseq_carve(uint8_t* base, int cap, int K, int P) {
     const MSeqCaps c = mseq_caps(cap, K, P);
     MSeqMem m;
-    m.mx = reinterpret_cast<uint64_t*>(base);
+    m.mx = reinterpret_cast<uint64_t*>(base);  // 16-byte aligned
     m.my = m.mx + c.cap;
-    m.hok = m.my + c.cap;
-    m.hxk = m.hok + c.ocap;
-    m.hyk = m.hxk + c.icap;
-    m.hor = reinterpret_cast<uint32_t*>(m.hyk + c.icap);
-    m.hxr = m.hor + c.ocap;
-    m.hyr = m.hxr + c.icap;
+    m.ho = reinterpret_cast<hent_t*>(m.my + c.cap);  // 16 * cap bytes in: still aligned
+    m.hx = m.ho + c.ocap;
+    m.hy = m.hx + c.icap;
     m.cap = c.cap;
     m.ocap = c.ocap;
     return m;
@@ -591,8 +607,7 @@ struct PairMSeq {
         int& cnt = isx ? cx : cy;
         int& hn = isx ? hxn : hyn;
         uint64_t* M = isx ? c.m.mx : c.m.my;
-        uint64_t* hk = isx ? c.m.hxk : c.m.hyk;
-        uint32_t* hr = isx ? c.m.hxr : c.m.hyr;
+        hent_t* hp = isx ? c.m.hx : c.m.hy;
         while (uint32_t(cnt) <= e) {
             if (hn == 0) return false;
             if (cnt >= c.m.cap) {
@@ -601,11 +616,11 @@ struct PairMSeq {
             }
             uint64_t key;
             uint32_t rk;
-            heap_pop(hk, hr, hn, key, rk);
+            heap_pop(hp, hn, key, rk);
             M[cnt++] = key;
             const uint32_t ra = rk >> 8, rb = rk & 0xFF;
-            if (rb + 1 < uint32_t(c.K)) heap_push(hk, hr, hn, inner_key(c, la, lb, ra, rb + 1), (ra << 8) | (rb + 1));
-            if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hk, hr, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
+            if (rb + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra, rb + 1), (ra << 8) | (rb + 1));
+            if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
         }
         sum = key_dist(M[e]);
         lid = key_id(M[e]);
@@ -618,7 +633,7 @@ struct PairMSeq {
             of = true;
             return;
         }
-        heap_push(c.m.hok, c.m.hor, hon, make_key(add(sx, sy), c.n + lx * c.sizeY + ly), (i << 16) | j);
+        heap_push(c.m.ho, hon, make_key(add(sx, sy), c.n + lx * c.sizeY + ly), (i << 16) | j);
         maxf = max(maxf, hon);
     }
     // the next call of next() may need an element or frontier entry beyond
@@ -633,15 +648,15 @@ struct PairMSeq {
     __device__ void init(const MSeqConf& c) {
         cx = cy = hxn = hyn = hon = maxf = 0;
         of = false;
-        if (c.nx == 2) heap_push(c.m.hxk, c.m.hxr, hxn, inner_key(c, c.ax, c.bx, 0, 0), 0u);
-        if (c.ny == 2) heap_push(c.m.hyk, c.m.hyr, hyn, inner_key(c, c.ay, c.by, 0, 0), 0u);
+        if (c.nx == 2) heap_push(c.m.hx, hxn, inner_key(c, c.ax, c.bx, 0, 0), 0u);
+        if (c.ny == 2) heap_push(c.m.hy, hyn, inner_key(c, c.ay, c.by, 0, 0), 0u);
         outer_push(c, 0, 0);
     }
     // the next bridge in (distance, lid) order; false when exhausted or overflowed
     __device__ bool next(const MSeqConf& c, uint64_t& key) {
         if (hon == 0 || of) return false;
         uint32_t pos;
-        heap_pop(c.m.hok, c.m.hor, hon, key, pos);
+        heap_pop(c.m.ho, hon, key, pos);
         const uint32_t i = pos >> 16, j = pos & 0xFFFF;
         if (j + 1 < c.sizeY) outer_push(c, i, j + 1);
         if (j == 0 && i + 1 < c.sizeX) outer_push(c, i + 1, 0);
@@ -715,6 +730,7 @@ k_search(SearchArgs a) {
             for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
         }
         __syncthreads();
+        const uint32_t qq = (MODE == MODE_U8 && NC16 == 8) ? query_norm_u8(qv, 128) : 0u;
 
         // ---- tables and their sort (the raw tables use the visited set's
         //      memory, cleared afterwards); the nearest bridge seeds the frontier
@@ -865,7 +881,7 @@ k_search(SearchArgs a) {
                                 else
                                     need = true;
                             }
-                            const uint32_t gdist = gather_need<MODE, NC16>(a, qv, pid, need, gid, gd, lane);
+                            const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, pid, need, gid, gd, lane);
                             if constexpr (COUNT) st_rows += __popcll(__ballot(need));
                             pre_d[sl] = need ? gdist : d;
                         }
@@ -908,18 +924,9 @@ k_search(SearchArgs a) {
                                 const MSeqMem g = ms_conf().m;
                                 for (int i = lane; i < sc[7]; i += WAVE) g.mx[i] = l.mx[i];
                                 for (int i = lane; i < sc[8]; i += WAVE) g.my[i] = l.my[i];
-                                for (int i = lane; i < sc[9]; i += WAVE) {
-                                    g.hxk[i] = l.hxk[i];
-                                    g.hxr[i] = l.hxr[i];
-                                }
-                                for (int i = lane; i < sc[10]; i += WAVE) {
-                                    g.hyk[i] = l.hyk[i];
-                                    g.hyr[i] = l.hyr[i];
-                                }
-                                for (int i = lane; i < sc[11]; i += WAVE) {
-                                    g.hok[i] = l.hok[i];
-                                    g.hor[i] = l.hor[i];
-                                }
+                                for (int i = lane; i < sc[9]; i += WAVE) g.hx[i] = l.hx[i];
+                                for (int i = lane; i < sc[10]; i += WAVE) g.hy[i] = l.hy[i];
+                                for (int i = lane; i < sc[11]; i += WAVE) g.ho[i] = l.ho[i];
                             }
                             __syncthreads();
                         }
@@ -962,7 +969,11 @@ k_search(SearchArgs a) {
                     }
                     ac_id = ID_EMPTY;
                     const uint32_t nd_l = uint32_t(__shfl(int(acn), row_lane_slot));
-                    if (R > 0 && lane < ns * R) ac_id = a.G[int64_t(nd_l) * R + row_lane_j];
+                    // the lane's column is re-stated here so that no per-lane row
+                    // pointer is kept (and spilled) across the search
+                    int col = row_lane_j;
+                    asm("" : "+v"(col));
+                    if (R > 0 && lane < ns * R) ac_id = a.G[int64_t(nd_l) * R + col];
                     bool need = false, known = false;
                     int slot = 0;
                     if (ac_id != ID_EMPTY && set_find(H, a.hash_buckets, ac_id) < 0) {
@@ -974,7 +985,7 @@ k_search(SearchArgs a) {
                             known = false;
                         }
                     }
-                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, ac_id, need, gid, gd, lane);
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, ac_id, need, gid, gd, lane);
                     if (need) DV[slot] = gdist;
                     const int m = __popcll(__ballot(need));
                     dc_fill += m;
@@ -1018,7 +1029,7 @@ k_search(SearchArgs a) {
                 } else {
                     const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
                     const bool miss = ev && slot < 0;
-                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
                     dist = slot >= 0 ? DV[slot] : gdist;
                 }
@@ -1046,7 +1057,7 @@ k_search(SearchArgs a) {
                     ev = white && r < take;
                     const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
                     const bool miss = ev && slot < 0;
-                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, id, miss, gid, gd, lane);
+                    const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
                     dist = slot >= 0 ? DV[slot] : gdist;
                     if (c0 + WAVE >= len || t + take >= T) break;
@@ -1367,11 +1378,13 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // The state is only fast in LDS: a query that outgrows it continues at L2
     // latency, one lane at a time.  With four lists of at most 64 codewords
     // a query at T <= 2048 expands about one bridge and 8 elements per side
-    // suffice; with three lists or K >= 100 (fewer, larger sides, more
-    // bridges expanded) the state gets 256.
+    // suffice; with three lists or K >= 100 (fewer, larger sides, and tens
+    // to hundreds of bridges expanded per query) the state gets 256, or 512
+    // when the whole batch is still resident at that size (below), and the
+    // short bridge lists are fetched ahead at every budget.
     const bool few_bridges = idx->P >= 4 && idx->K <= 64;
     a.ms_cap = int(std::min<int64_t>(side, s.Tmax <= 2048 && few_bridges ? 8 : 256));
-    a.prefetch = s.Tmax > 2048 ? 1 : 0;
+    a.prefetch = (s.Tmax > 2048 || !few_bridges) ? 1 : 0;
     a.gen_batch = s.Tmax <= 2048 ? 16 : GEN_BATCH;
 
     const int qbytes = pl.is_f32 ? idx->d * 4 : idx->d;
@@ -1379,6 +1392,18 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     pl.rcap = pl.bf16 ? std::max(s.kmax, a.rerank_k) : s.kmax;
     ANN_REQUIRE(pl.rcap <= 1024, "search: k (or rerank_k) above 1024");
     const int lpr = pl.is_f32 ? (pl.bf16 ? Traits<MODE_BF16>::LPR : Traits<MODE_F32>::LPR) : Traits<MODE_U8>::LPR;
+    int cus = 0, lds_cu = 0;
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, idx->device));
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, idx->device));
+    if (!few_bridges && a.ms_cap < side) {
+        // a batch that fits on the chip either way: the larger state keeps
+        // the bridge-heavy queries (the launch's slowest) in LDS
+        SearchArgs big = a;
+        big.ms_cap = int(std::min<int64_t>(side, 512));
+        const int lds_big = layout(big, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+        const int64_t granules = ceil_div(lds_big, kLdsGranule);
+        if (int64_t(cus) * (lds_cu / (granules * kLdsGranule)) >= s.nq) a.ms_cap = big.ms_cap;
+    }
     pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
     {
         // LDS is allocated to a workgroup in granules of 2.5 KB: a larger
@@ -1395,9 +1420,6 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // order | global multi-sequence slots (a side holds at most K^2 elements)
     pl.gcap = std::min<int64_t>(int64_t(idx->K) * idx->K, 8192);
     pl.slot_bytes = size_t(mseq_slot_bytes(int(pl.gcap), idx->K, idx->P));
-    int cus = 0, lds_cu = 0;
-    ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, idx->device));
-    ANN_HIP_CHECK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, idx->device));
     const int64_t resident = int64_t(cus) * std::max(1, std::min(32, lds_cu / std::max(1, pl.lds1)));
     int64_t slots = s.Tmax > 2048 ? resident : kSmallBudgetSlots;
     slots = std::min<int64_t>(slots, int64_t(kMaxSlotBytes / pl.slot_bytes));
