@@ -962,11 +962,7 @@ k_search(SearchArgs a) {
                         __syncthreads();
                     }
                     const int ns = min(S, qn);
-                    acn = ID_EMPTY;
-                    for (int s = 0; s < ns; ++s) {
-                        const uint32_t nd = key_id(readlane64(Qv[0], s));
-                        if (lane == s) acn = nd;
-                    }
+                    acn = lane < ns ? key_id(Qv[0]) : ID_EMPTY;  // lane s holds queue entry s
                     ac_id = ID_EMPTY;
                     const uint32_t nd_l = uint32_t(__shfl(int(acn), row_lane_slot));
                     // the lane's column is re-stated here so that no per-lane row
