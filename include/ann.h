@@ -273,8 +273,11 @@ int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq
  * Launch autotuner: times the launch-tuning choices of ann_search_params
  * (lookahead, persistent, waves_per_cu, order) on the given device batch
  * and writes the fastest into *params; the other fields are kept.  Every
+ * candidate runs twice; the three fastest and the default are then timed
+ * five more times each, in turn, and the lowest median wins.  Every
  * candidate must return the same ids; a difference is reported as
- * ANN_ESTATE.  Synchronous on `stream`.
+ * ANN_ESTATE.  Allocates two nq x k output buffers for the duration of the
+ * call.  Synchronous on `stream`.
  */
 int ann_autotune(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
                  const int32_t* d_k, const int32_t* d_budget, ann_search_params* params, void* stream);

@@ -357,6 +357,11 @@ __device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& f
     return -1;
 }
 
+// The distance cache's values carry a visited flag in their top bit (u8
+// distances stay below 2^31 for d <= 512; fp32 distances are non-negative).
+constexpr uint32_t VISITED_FLAG = 0x80000000u;
+constexpr uint32_t DIST_BITS = 0x7FFFFFFFu;
+
 // Slot of id, or -1.
 __device__ inline int set_find(const uint32_t* T, uint32_t nbk, uint32_t id) {
     uint32_t b = home_bucket(id, nbk);
@@ -404,11 +409,10 @@ __device__ inline uint64_t wave_shl1(uint64_t v, uint64_t fill) {
     return (uint64_t(hi) << 32) | lo;
 }
 
-// v with lane l replaced by the wave-uniform value x (v_writelane_b32; the
-// lane select goes through m0, as two scalar operands would exceed the
-// constant bus)
+// v with lane l replaced by the wave-uniform value x (v_writelane_b32, its
+// lane select in m0: two scalar operands would exceed the constant bus)
 __device__ inline int write_lane(int v, int x, int l) {
-    asm("s_mov_b32 m0, %2\n\ts_nop 0\n\tv_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(x), "s"(l) : "m0");
+    asm("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(x), "{m0}"(l));
     return v;
 }
 
@@ -770,6 +774,13 @@ k_search(SearchArgs a) {
         // look-ahead rows: lane l holds neighbour (l % R) of entry (l / R)
         uint32_t acn = ID_EMPTY;  // lane s < S: node id of entry s
         uint32_t ac_id = ID_EMPTY, ac_d = 0;
+        // visits of a look-ahead window: a lane's neighbour that was unvisited
+        // when its row was loaded has a distance-cache slot (ac_slot); a pop
+        // marks it visited with one atomic on that slot's flag, and the
+        // window's marks (pend) enter the visited set in one pass before the
+        // set is read again
+        int ac_slot = -1;
+        bool pend = false;
         int t = 0;
         int dc_fill = 0;
         int st_rpop = 0, st_bpop = 0, st_bids = 0, st_gen = 0, st_rows = 0, st_spec = 0;
@@ -792,7 +803,14 @@ k_search(SearchArgs a) {
             if (__ballot(qa)) reg_merge1(Qv[0], qn, a.L, key, qa, lane, mrg);
         };
 
+        auto flush = [&](bool& full) {
+            bool fresh = false;
+            if (pend && set_insert(H, a.hash_buckets, ac_id, fresh) < 0) full = true;
+            pend = false;
+        };
+
         while (t < T) {
+            bool full = false;
             // ---- look-ahead extraction of the next non-empty bridges; their
             //      lists (and, once bridges are in use, their distances) are
             //      fetched with them: the bridge order does not depend on the
@@ -863,6 +881,7 @@ k_search(SearchArgs a) {
                     __syncthreads();
                     ++refills;
                     const bool with_dist = refills >= 2;
+                    if (a.prefetch && with_dist) flush(full);
 #pragma unroll 1
                     for (int u = 0; a.prefetch && u < GEN_BATCH * PRE_LIST / WAVE; ++u) {
                         const int sl = lane + u * WAVE;
@@ -877,7 +896,7 @@ k_search(SearchArgs a) {
                             if (pid != ID_EMPTY && set_find(H, a.hash_buckets, pid) < 0) {
                                 const int ds = set_find(DK, a.dc_buckets, pid);
                                 if (ds >= 0)
-                                    d = DV[ds];
+                                    d = DV[ds] & DIST_BITS;
                                 else
                                     need = true;
                             }
@@ -945,7 +964,7 @@ k_search(SearchArgs a) {
                 break;
             }
 
-            bool ev = false, full = false;
+            bool ev = false;
             uint32_t id = ID_EMPTY, dist = 0;
             int take = 0;
             if (!use_bridge) {
@@ -956,20 +975,24 @@ k_search(SearchArgs a) {
                     // work ahead: rows of the S best queue entries, distances of
                     // their unvisited neighbours not yet in the cache
                     if constexpr (COUNT) ++st_spec;
-                    if (dc_fill > dc_limit) {
-                        for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
-                        dc_fill = 0;
-                        __syncthreads();
-                    }
                     const int ns = min(S, qn);
                     acn = lane < ns ? key_id(Qv[0]) : ID_EMPTY;  // lane s holds queue entry s
-                    ac_id = ID_EMPTY;
                     const uint32_t nd_l = uint32_t(__shfl(int(acn), row_lane_slot));
                     // the lane's column is re-stated here so that no per-lane row
                     // pointer is kept (and spilled) across the search
                     int col = row_lane_j;
                     asm("" : "+v"(col));
-                    if (R > 0 && lane < ns * R) ac_id = a.G[int64_t(nd_l) * R + col];
+                    uint32_t nid = ID_EMPTY;
+                    if (R > 0 && lane < ns * R) nid = a.G[int64_t(nd_l) * R + col];
+                    // while the rows load: the last window's visits enter the
+                    // visited set, and the distance cache is cleared when half full
+                    flush(full);
+                    if (dc_fill > dc_limit) {
+                        for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
+                        dc_fill = 0;
+                        lds_wave_order();
+                    }
+                    ac_id = nid;
                     bool need = false, known = false;
                     int slot = 0;
                     if (ac_id != ID_EMPTY && set_find(H, a.hash_buckets, ac_id) < 0) {
@@ -987,7 +1010,8 @@ k_search(SearchArgs a) {
                     dc_fill += m;
                     if constexpr (COUNT) st_rows += m;
                     __syncthreads();
-                    ac_d = known ? (need ? gdist : DV[slot]) : 0u;
+                    ac_d = known ? (need ? gdist : (DV[slot] & DIST_BITS)) : 0u;
+                    ac_slot = known ? slot : -1;
                     hit = 1;  // entry 0 is the queue head
                 }
                 const int s = __builtin_ctzll(hit);
@@ -995,8 +1019,11 @@ k_search(SearchArgs a) {
                 if constexpr (COUNT) ++st_rpop;
                 // ---- expand: the row sits in lanes [s*R, s*R + R)
                 const bool inrow = R > 0 && row_lane_slot == s && lane < (s + 1) * R;
+                // unvisited when the row was loaded, and not visited since unless
+                // a pop or a bridge of this window set the slot's flag
                 bool white = false;
-                if (inrow && ac_id != ID_EMPTY && set_insert(H, a.hash_buckets, ac_id, white) < 0) full = true;
+                if (inrow && ac_slot >= 0) white = (atomicOr(&DV[ac_slot], VISITED_FLAG) & VISITED_FLAG) == 0u;
+                pend = pend || white;
                 const uint64_t wm = __ballot(white);
                 take = min(int(__popcll(wm)), T - t);
                 r = lanes_below(wm);
@@ -1014,20 +1041,24 @@ k_search(SearchArgs a) {
                     st_bids += len;
                 }
                 id = lane < len ? pre_id[e * PRE_LIST + lane] : ID_EMPTY;
+                flush(full);
                 bool white = false;
                 if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
                 const uint64_t wm = __ballot(white);
                 take = min(int(__popcll(wm)), T - t);
                 r = lanes_below(wm);
                 ev = white && r < take;
+                // an evaluated id with a cache slot flags it, so that the rows
+                // of the current window see the visit
+                const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
+                const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
                 if ((dist_mask >> e) & 1u) {
                     dist = pre_d[e * PRE_LIST + lane];  // measured ahead: white then, so not visited then
                 } else {
-                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
                     const bool miss = ev && slot < 0;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
-                    dist = slot >= 0 ? DV[slot] : gdist;
+                    dist = slot >= 0 ? cached : gdist;
                 }
             } else {
                 // ---- a bridge with a long list: walked from global memory
@@ -1042,6 +1073,7 @@ k_search(SearchArgs a) {
                 // lists longer than a wave are walked in chunks; every chunk but
                 // the one that ends the list or the budget is merged here, that
                 // one below
+                flush(full);
                 for (int c0 = 0;; c0 += WAVE) {
                     const int j = c0 + lane;
                     id = j < len ? a.bids[base + j] : ID_EMPTY;
@@ -1052,10 +1084,11 @@ k_search(SearchArgs a) {
                     r = lanes_below(wm);
                     ev = white && r < take;
                     const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
+                    const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
                     const bool miss = ev && slot < 0;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
-                    dist = slot >= 0 ? DV[slot] : gdist;
+                    dist = slot >= 0 ? cached : gdist;
                     if (c0 + WAVE >= len || t + take >= T) break;
                     offer(make_key(dist, id), ev);
                     t += take;
