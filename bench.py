@@ -144,6 +144,13 @@ def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
             "plain_saturation_rps": round(sat, 2), "runs": runs, **checks}
 
 
+def bridge_alpha(idx):
+    """Share of the K^P bridge vectors that hold at least one reference
+    vector (the paper's alpha, Table 1), from the exported CSR offsets."""
+    off = np.asarray(idx.export()["bridge_off"], dtype=np.int64)
+    return float(np.count_nonzero(np.diff(off))) / max(1, len(off) - 1)
+
+
 def bench_uneven(w, args, torch):
     """The 10M workload: 100K queries with their own k (1, 10, 100) and budget
     (log-uniform 64..4096) searched by one persistent launch captured in a HIP
@@ -160,6 +167,8 @@ def bench_uneven(w, args, torch):
     torch.cuda.synchronize()
     build_s = time.time() - t0
     log(f"[bench] index built in {build_s:.1f}s: {idx.info}")
+    alpha = bridge_alpha(idx)
+    log(f"[bench] bridges holding at least one vector: {alpha:.4f} of K^P")
     xd = torch.from_numpy(X).cuda()
     qd = torch.from_numpy(Q).cuda()
     gt, _ = knn_device(xd, qd, 10)
@@ -247,7 +256,8 @@ def bench_uneven(w, args, torch):
                    "budget": "log-uniform 64..4096", "mean_budget": round(float(Ts.mean()), 1),
                    "queue_len": w.queue_len, "graph_k": w.graph_k, "P": w.P, "K": w.K, "bridge_t": w.bridge_t,
                    "bridge_b": w.bridge_b, "recall@10_k>=10": round(rec, 4), "launch": tune,
-                   "hip_graph": True, "graph_ids_equal_eager": same, "build_s": round(build_s, 2)},
+                   "hip_graph": True, "graph_ids_equal_eager": same, "build_s": round(build_s, 2),
+                   "bridge_alpha": round(alpha, 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_search",
                      "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": int(B.sum())},
@@ -301,6 +311,8 @@ def main():
     ap.add_argument("--serve-mixed", action="store_true",
                     help="also serve a stream with k in {1,10,100} and budgets 128..8192 per request")
     ap.add_argument("--serve-pool", type=int, default=200_000, help="query vectors the request streams draw")
+    ap.add_argument("--bridge-t", type=int, default=-1, help="override the workload's bridges per vector (t)")
+    ap.add_argument("--bridge-b", type=int, default=-1, help="override the workload's vectors per bridge (b; 0 = all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a copy-like kernel over 1 GiB (calibrates hardware traffic counters)")
     args = ap.parse_args()
@@ -315,6 +327,11 @@ def main():
     from paper_1312_3062_amd import Index, knn_device, recall_at, synth
 
     w = synth.WORKLOADS[args.workload]
+    overridden = args.bridge_t >= 0 or args.bridge_b >= 0
+    if overridden:
+        import dataclasses
+        w = dataclasses.replace(w, bridge_t=w.bridge_t if args.bridge_t < 0 else args.bridge_t,
+                                bridge_b=w.bridge_b if args.bridge_b < 0 else args.bridge_b)
     if w.variable_kT:
         bench_uneven(w, args, torch)
         return
@@ -329,6 +346,8 @@ def main():
     build_s = time.time() - t0
     info = idx.info
     log(f"[bench] index built in {build_s:.1f}s: {info}")
+    alpha = bridge_alpha(idx)
+    log(f"[bench] bridges holding at least one vector: {alpha:.4f} of K^P")
 
     xd = torch.from_numpy(X).cuda()
     qd = torch.from_numpy(Q).cuda()
@@ -438,7 +457,8 @@ def main():
     # profiles (only if taken on the current kernel sources and this workload)
     from paper_1312_3062_amd.profiling import read_traffic_record
     trec = read_traffic_record(os.path.join(ROOT, "profiles", f"k_search_{w.name}_traffic.md"))
-    traffic = trec["bytes_per_launch"] if trec and trec.get("workload") == f"{w.name} T={T} nq={nq}" else None
+    traffic = (trec["bytes_per_launch"] if trec and trec.get("workload") == f"{w.name} T={T} nq={nq}" and not overridden
+               else None)
 
     precision = None
     if X.dtype == np.float32:
@@ -504,7 +524,7 @@ def main():
                    "bridge_t": w.bridge_t, "bridge_b": w.bridge_b, "recall@10": round(rec, 4),
                    "budget_sweep": sweep, "launch": tune, "build_s": round(build_s, 2),
                    "plain_qps": round(nq * args.steps / plain_wall, 1), "plain_kernel_ms": round(plain_kms, 4),
-                   "host_buffers_qps": round(host_qps, 1)},
+                   "host_buffers_qps": round(host_qps, 1), "bridge_alpha": round(alpha, 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
