@@ -249,8 +249,9 @@ int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, i
 
 /*
  * Device workspace for ann_search_device_ws and this request (bytes): the
- * per-query lists plus 256 global slots for multi-sequence state that
- * outgrows LDS.
+ * per-query lists plus global slots for multi-sequence state that outgrows
+ * LDS (256 slots up to a budget of 2048, one per resident query above it,
+ * never more than the batch's queries or 512 MB).
  */
 int ann_search_workspace_size(const ann_index* idx, int64_t nq, int32_t k, int32_t budget,
                               const ann_search_params* params, int64_t* bytes);
