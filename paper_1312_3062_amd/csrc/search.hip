@@ -1023,6 +1023,7 @@ k_search(SearchArgs a) {
                 // a pop or a bridge of this window set the slot's flag
                 bool white = false;
                 if (inrow && ac_slot >= 0) white = (atomicOr(&DV[ac_slot], VISITED_FLAG) & VISITED_FLAG) == 0u;
+                if (inrow) ac_slot = -1;  // the row is expanded
                 pend = pend || white;
                 const uint64_t wm = __ballot(white);
                 take = min(int(__popcll(wm)), T - t);
@@ -1048,13 +1049,21 @@ k_search(SearchArgs a) {
                 take = min(int(__popcll(wm)), T - t);
                 r = lanes_below(wm);
                 ev = white && r < take;
-                // an evaluated id with a cache slot flags it, so that the rows
-                // of the current window see the visit
-                const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
-                const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
                 if ((dist_mask >> e) & 1u) {
                     dist = pre_d[e * PRE_LIST + lane];  // measured ahead: white then, so not visited then
+                    // the window's unexpanded rows see these (at most 8) visits:
+                    // lanes holding one of the ids give up their cache slot
+                    uint64_t evm = __ballot(ev);
+                    while (evm) {
+                        const int j = __builtin_ctzll(evm);
+                        evm &= evm - 1;
+                        if (ac_id == uint32_t(__builtin_amdgcn_readlane(int(id), j))) ac_slot = -1;
+                    }
                 } else {
+                    // an evaluated id with a cache slot flags it, so that the
+                    // rows of the current window see the visit
+                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
+                    const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
                     const bool miss = ev && slot < 0;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
