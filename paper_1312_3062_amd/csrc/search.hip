@@ -775,10 +775,12 @@ k_search(SearchArgs a) {
         uint32_t acn = ID_EMPTY;  // lane s < S: node id of entry s
         uint32_t ac_id = ID_EMPTY, ac_d = 0;
         // visits of a look-ahead window: a lane's neighbour that was unvisited
-        // when its row was loaded has a distance-cache slot (ac_slot); a pop
-        // marks it visited with one atomic on that slot's flag, and the
-        // window's marks (pend) enter the visited set in one pass before the
-        // set is read again
+        // when its row was loaded keeps a distance-cache slot (ac_slot) until
+        // its row is expanded or a bridge with prefetched distances visits it.
+        // Expanding the row marks the visit with one atomic on that slot's
+        // flag (bridges with long lists set the flags of the ids they visit);
+        // the window's marks (pend) enter the visited set in one pass before
+        // the set is read again
         int ac_slot = -1;
         bool pend = false;
         int t = 0;

@@ -12,8 +12,8 @@
       out, which removes the counters' own scale.  Prints a markdown summary
       and one machine-readable line (an HTML comment) that bench.py reads.
 
-The machine-readable line carries a hash of the search kernel's sources:
-a figure taken on other sources is not reported.
+The machine-readable line carries a hash of the search kernel's code
+(comments aside): a figure taken on other code is not reported.
 """
 from __future__ import annotations
 
@@ -32,10 +32,15 @@ TRAFFIC_TAG = "traffic-record"
 
 
 def kernel_source_hash() -> str:
+    """Hash of the search kernel's code: comments, indentation and blank
+    lines are left out, so that only a change of the code itself retires a
+    traffic record (the sources hold no string with `//` or `/*`)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(PKG, rel), "rb") as f:
-            h.update(rel.encode() + b"\0" + f.read())
+        with open(os.path.join(PKG, rel), encoding="utf-8") as f:
+            text = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+        code = [ln.split("//", 1)[0].strip() for ln in text.splitlines()]
+        h.update(rel.encode() + b"\0" + "\n".join(c for c in code if c).encode())
     return h.hexdigest()[:16]
 
 
