@@ -231,6 +231,7 @@ VARIANTS = [
     (1200, 64, 4, 6, 12, 100, 5, 3, 256),
     (800, 128, 4, 3, 3, 2, 1, 1, 4),     # tie-heavy, tiny lists
     (1300, 256, 2, 16, 16, 4, 3, 6, 256),
+    (600, 512, 4, 8, 6, 2, 0, 2, 256),   # the largest u8 rows (512 bytes) and distances
 ]
 
 
@@ -310,6 +311,30 @@ def test_bridge_heavy_search_bit_exact(n, P, K, t, b, T, k):
     assert_search_equal(idx, parts, X, Q, k, T, 64)
 
 
+def test_state_capacity_by_batch_size():
+    """Three lists of 100 codewords: a batch that stays resident with 512
+    multi-sequence elements per query in LDS gets them, a larger batch gets
+    256 (short bridge lists are fetched ahead either way).  Both give the
+    oracle's results, query by query."""
+    rng = np.random.default_rng(31)
+    n = 6000
+    X = rng.integers(0, 256, size=(n, 48)).astype(np.uint8)
+    Q = rng.integers(0, 256, size=(3000, 48)).astype(np.uint8)
+    idx = _index_cls().build(X, 8, 3, 100, 3, 17, 10, 5)
+    parts = idx.export()
+    gi, gd, st = gpu_search(idx, Q, 10, 600, 64, stats=True)        # more than the chip holds at 512
+    si, sd = gpu_search(idx, Q[:200], 10, 600, 64)                  # resident at 512
+    assert (st[:, 6] == 0).all()
+    assert (st[:, 2] > 5).mean() > 0.5       # bridges are expanded throughout
+    np.testing.assert_array_equal(si, gi[:200])
+    np.testing.assert_array_equal(sd, gd[:200])
+    rows = np.arange(0, len(Q), 5)          # every fifth query against the oracle
+    oi, od = oracle.search(X, parts["codebooks"], parts["graph"], parts["bridge_off"], parts["bridge_ids"], Q[rows],
+                           10, 600, 64)
+    np.testing.assert_array_equal(gi[rows], oi)
+    np.testing.assert_array_equal(gd[rows].astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
+
+
 def _overflow_case():
     rng = np.random.default_rng(77)
     n = 2000
@@ -320,8 +345,9 @@ def _overflow_case():
 
 
 def test_multisequence_overflow_moves_to_a_global_slot_exactly():
-    """At T <= 2048 the LDS enumeration holds 64 elements per side; a query that
-    needs more carries on with its state in a global slot."""
+    """At T <= 2048, with four lists of at most 64 codewords, the LDS
+    enumeration holds 8 elements per side; a query that needs more carries on
+    with its state in a global slot."""
     X, Q, idx, parts = _overflow_case()
     gi, gd, st = gpu_search(idx, Q, 10, 1800, 64, stats=True)
     assert (st[:, 10] == 1).any()           # some queries outgrew the LDS capacity
