@@ -145,10 +145,15 @@ def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
 
 
 def bridge_alpha(idx):
-    """Share of the K^P bridge vectors that hold at least one reference
-    vector (the paper's alpha, Table 1), from the exported CSR offsets."""
-    off = np.asarray(idx.export()["bridge_off"], dtype=np.int64)
-    return float(np.count_nonzero(np.diff(off))) / max(1, len(off) - 1)
+    """The bridge graph's occupancy, from the exported CSR: alpha as in the
+    paper's Table 1 (reference vectors linked to some bridge, per bridge
+    vector: #linked / K^P) and the share of bridge vectors whose list is not
+    empty."""
+    parts = idx.export()
+    off = np.asarray(parts["bridge_off"], dtype=np.int64)
+    nb = max(1, len(off) - 1)
+    linked = np.unique(np.asarray(parts["bridge_ids"])[:int(off[-1])]).size
+    return {"alpha": linked / nb, "linked": int(linked), "nonempty_share": float(np.count_nonzero(np.diff(off))) / nb}
 
 
 def bench_uneven(w, args, torch):
@@ -168,7 +173,8 @@ def bench_uneven(w, args, torch):
     build_s = time.time() - t0
     log(f"[bench] index built in {build_s:.1f}s: {idx.info}")
     alpha = bridge_alpha(idx)
-    log(f"[bench] bridges holding at least one vector: {alpha:.4f} of K^P")
+    log(f"[bench] bridge graph: {alpha['linked']} reference vectors linked, alpha {alpha['alpha']:.4f}; "
+        f"{alpha['nonempty_share']:.4f} of the K^P lists not empty")
     xd = torch.from_numpy(X).cuda()
     qd = torch.from_numpy(Q).cuda()
     gt, _ = knn_device(xd, qd, 10)
@@ -257,7 +263,7 @@ def bench_uneven(w, args, torch):
                    "queue_len": w.queue_len, "graph_k": w.graph_k, "P": w.P, "K": w.K, "bridge_t": w.bridge_t,
                    "bridge_b": w.bridge_b, "recall@10_k>=10": round(rec, 4), "launch": tune,
                    "hip_graph": True, "graph_ids_equal_eager": same, "build_s": round(build_s, 2),
-                   "bridge_alpha": round(alpha, 5)},
+                   "bridge_alpha": round(alpha["alpha"], 5), "bridges_nonempty": round(alpha["nonempty_share"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_search",
                      "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": int(B.sum())},
@@ -347,7 +353,8 @@ def main():
     info = idx.info
     log(f"[bench] index built in {build_s:.1f}s: {info}")
     alpha = bridge_alpha(idx)
-    log(f"[bench] bridges holding at least one vector: {alpha:.4f} of K^P")
+    log(f"[bench] bridge graph: {alpha['linked']} reference vectors linked, alpha {alpha['alpha']:.4f}; "
+        f"{alpha['nonempty_share']:.4f} of the K^P lists not empty")
 
     xd = torch.from_numpy(X).cuda()
     qd = torch.from_numpy(Q).cuda()
@@ -524,7 +531,8 @@ def main():
                    "bridge_t": w.bridge_t, "bridge_b": w.bridge_b, "recall@10": round(rec, 4),
                    "budget_sweep": sweep, "launch": tune, "build_s": round(build_s, 2),
                    "plain_qps": round(nq * args.steps / plain_wall, 1), "plain_kernel_ms": round(plain_kms, 4),
-                   "host_buffers_qps": round(host_qps, 1), "bridge_alpha": round(alpha, 5)},
+                   "host_buffers_qps": round(host_qps, 1),
+                   "bridge_alpha": round(alpha["alpha"], 5), "bridges_nonempty": round(alpha["nonempty_share"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",

@@ -99,10 +99,14 @@ def test_algorithmic_bytes_counts_each_term():
     assert b[1] == 10 * 128 + 32 * 8 + 10 * 4 + 128 + 80
 
 
-def test_bridge_alpha_is_the_share_of_nonempty_lists():
-    off = np.array([0, 0, 3, 3, 4, 4, 4, 9], np.uint32)   # 7 bridges, 3 hold vectors
-    idx = SimpleNamespace(export=lambda: {"bridge_off": off})
-    assert bench.bridge_alpha(idx) == pytest.approx(3 / 7)
+def test_bridge_alpha_counts_linked_vectors_per_bridge():
+    off = np.array([0, 0, 3, 3, 4, 4, 4, 9], np.uint32)   # 7 bridges, 3 lists not empty
+    ids = np.array([5, 1, 2, 5, 7, 8, 1, 9, 2], np.uint32)  # 6 distinct reference vectors
+    idx = SimpleNamespace(export=lambda: {"bridge_off": off, "bridge_ids": ids})
+    a = bench.bridge_alpha(idx)
+    assert a["linked"] == 6
+    assert a["alpha"] == pytest.approx(6 / 7)
+    assert a["nonempty_share"] == pytest.approx(3 / 7)
 
 
 def test_oracle_on_all_cores_matches_the_single_threaded_oracle():
