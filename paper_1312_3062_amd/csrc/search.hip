@@ -1402,11 +1402,12 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.trace = s.d_trace;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates); buckets for a final load of about 0.85.  The
-    // distance cache (cleared when half full) gets at least 64 buckets and
-    // grows into the slack of the last LDS granule (below).
-    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 20 / 17 / 4 + 1));
-    a.dc_buckets = 64;
+    // than it evaluates); buckets for a final load of about 0.8 (its lookups
+    // sit on the look-ahead's critical path: at 0.92 the 1M x 128 search took
+    // 15% longer).  The distance cache (cleared when half full) gets at least
+    // 56 buckets and grows into the slack of the last LDS granule (below).
+    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
+    a.dc_buckets = 56;
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
     // multi-sequence capacity in LDS (materialised side elements and outer
@@ -1450,7 +1451,7 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
         // distance cache that stays within the same granules costs no
         // residency (a bucket of keys and values is 32 bytes)
         const int slack = int(ceil_div(pl.lds1, kLdsGranule) * kLdsGranule) - pl.lds1;
-        a.dc_buckets = uint32_t(std::min(128, 64 + slack / 32));
+        a.dc_buckets = uint32_t(std::min(128, 56 + slack / 32));
         pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
     }
     pl.a2 = a;
