@@ -325,6 +325,16 @@ __device__ inline uint32_t home_bucket(uint32_t id, uint32_t nbk) {
     return uint32_t((uint64_t(id * 0x9E3779B1u) * nbk) >> 32);
 }
 
+// Lookups read two consecutive buckets at once (one LDS round trip); the
+// second counts only when the first is full, so the probe order is that of
+// bucket-by-bucket linear probing.
+__device__ inline int bucket_slot(uint4 v, uint32_t id) {
+    return v.x == id ? 0 : v.y == id ? 1 : v.z == id ? 2 : v.w == id ? 3 : -1;
+}
+__device__ inline int bucket_free(uint4 v) {
+    return v.x == ID_EMPTY ? 0 : v.y == ID_EMPTY ? 1 : v.z == ID_EMPTY ? 2 : v.w == ID_EMPTY ? 3 : -1;
+}
+
 // Slot of id, inserting it if absent.  fresh = it was absent.  Returns -1
 // (fresh = false) only if the table is full, which the callers' sizing rules
 // out; the probe count is bounded so that a wave can never spin here.
@@ -332,16 +342,12 @@ __device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& f
     uint32_t b = home_bucket(id, nbk);
     for (uint32_t step = 0; step < 5 * nbk + 4; ++step) {
         const uint4 v = reinterpret_cast<const uint4*>(T)[b];
-        int e = -1;
-        if (v.x == id) e = 0;
-        else if (v.y == id) e = 1;
-        else if (v.z == id) e = 2;
-        else if (v.w == id) e = 3;
+        const int e = bucket_slot(v, id);
         if (e >= 0) {
             fresh = false;
             return int(b * 4 + e);
         }
-        const int f = v.x == ID_EMPTY ? 0 : v.y == ID_EMPTY ? 1 : v.z == ID_EMPTY ? 2 : v.w == ID_EMPTY ? 3 : -1;
+        const int f = bucket_free(v);
         if (f < 0) {
             b = (b + 1 == nbk) ? 0 : b + 1;
             continue;
@@ -365,14 +371,17 @@ constexpr uint32_t DIST_BITS = 0x7FFFFFFFu;
 // Slot of id, or -1.
 __device__ inline int set_find(const uint32_t* T, uint32_t nbk, uint32_t id) {
     uint32_t b = home_bucket(id, nbk);
-    for (uint32_t step = 0; step < nbk; ++step) {
+    for (uint32_t step = 0; step < nbk; step += 2) {
+        const uint32_t b2 = (b + 1 == nbk) ? 0 : b + 1;
         const uint4 v = reinterpret_cast<const uint4*>(T)[b];
-        if (v.x == id) return int(b * 4);
-        if (v.y == id) return int(b * 4 + 1);
-        if (v.z == id) return int(b * 4 + 2);
-        if (v.w == id) return int(b * 4 + 3);
-        if (v.x == ID_EMPTY || v.y == ID_EMPTY || v.z == ID_EMPTY || v.w == ID_EMPTY) return -1;
-        b = (b + 1 == nbk) ? 0 : b + 1;
+        const uint4 w = reinterpret_cast<const uint4*>(T)[b2];
+        const int e = bucket_slot(v, id), e2 = bucket_slot(w, id);
+        const bool open = bucket_free(v) >= 0;
+        if (e >= 0) return int(b * 4 + e);
+        if (open) return -1;
+        if (e2 >= 0) return int(b2 * 4 + e2);
+        if (bucket_free(w) >= 0) return -1;
+        b = (b2 + 1 == nbk) ? 0 : b2 + 1;
     }
     return -1;
 }
