@@ -18,20 +18,40 @@ __device__ inline void compute_tables(const uint8_t* qv, const void* cb, int P, 
     for (int e = lane; e < PK; e += WAVE) {
         const int p = e / K;
         if constexpr (!FLOAT) {
-            const uint8_t* c = static_cast<const uint8_t*>(cb) + int64_t(e) * ds;
-            const uint8_t* q = qv + p * ds;
-            uint32_t acc = 0;
-            for (int i = 0; i < ds; ++i) {
-                int t = int(q[i]) - int(c[i]);
-                acc += uint32_t(t * t);
+            // u8 subvectors are a multiple of 4 bytes (d % 16 == 0, P <= 4):
+            // |q - c|^2 = q.q + c.c - 2 q.c by 4-byte dot products, exact
+            const uint32_t* c = reinterpret_cast<const uint32_t*>(static_cast<const uint8_t*>(cb) + int64_t(e) * ds);
+            const uint32_t* q = reinterpret_cast<const uint32_t*>(qv + p * ds);
+            uint32_t qq = 0, cc = 0, qc = 0;
+            for (int i = 0; i < ds / 4; ++i) {
+                const uint32_t qw = q[i], cw = c[i];
+                qq = __builtin_amdgcn_udot4(qw, qw, qq, false);
+                cc = __builtin_amdgcn_udot4(cw, cw, cc, false);
+                qc = __builtin_amdgcn_udot4(qw, cw, qc, false);
             }
-            tab[e] = acc;
+            tab[e] = qq + cc - 2u * qc;
         } else {
             const float* c = static_cast<const float*>(cb) + int64_t(e) * ds;
             const float* q = reinterpret_cast<const float*>(qv) + p * ds;
             float acc = 0.f;
-            for (int i = 0; i < ds; ++i) {
-                float t = q[i] - c[i];
+            int i = 0;
+            if (ds % 4 == 0) {
+                // 16-byte loads, the same order of operations as one at a time
+                for (; i < ds; i += 4) {
+                    const float4 cv = *reinterpret_cast<const float4*>(c + i);
+                    const float4 qv4 = *reinterpret_cast<const float4*>(q + i);
+                    float t = qv4.x - cv.x;
+                    acc = fmaf(t, t, acc);
+                    t = qv4.y - cv.y;
+                    acc = fmaf(t, t, acc);
+                    t = qv4.z - cv.z;
+                    acc = fmaf(t, t, acc);
+                    t = qv4.w - cv.w;
+                    acc = fmaf(t, t, acc);
+                }
+            }
+            for (; i < ds; ++i) {
+                const float t = q[i] - c[i];
                 acc = fmaf(t, t, acc);
             }
             tab[e] = f_bits(acc);
