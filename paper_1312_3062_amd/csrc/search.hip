@@ -709,7 +709,7 @@ k_search(SearchArgs a) {
     const int P = a.P, K = a.K, R = a.R;
     const int HW = int(a.hash_buckets) * 4;
     const int DW = int(a.dc_buckets) * 4;
-    const int dc_limit = DW / 2 - WAVE;  // keeps the cache at most about half full
+    const int dc_limit = DW * 5 / 8 - WAVE;  // keeps the cache at most about 5/8 full
     const int qbytes = FLOAT ? a.d * 4 : a.d;
     const int S = a.spec;
     const int row_lane_slot = R > 0 ? lane / R : 0;  // which look-ahead entry this lane serves
