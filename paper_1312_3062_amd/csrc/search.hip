@@ -996,7 +996,7 @@ k_search(SearchArgs a) {
                     uint32_t nid = ID_EMPTY;
                     if (R > 0 && lane < ns * R) nid = a.G[int64_t(nd_l) * R + col];
                     // while the rows load: the last window's visits enter the
-                    // visited set, and the distance cache is cleared when half full
+                    // visited set, and the distance cache is cleared when 5/8 full
                     flush(full);
                     if (dc_fill > dc_limit) {
                         for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
@@ -1413,7 +1413,7 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
     // than it evaluates); buckets for a final load of about 0.8 (its lookups
     // sit on the look-ahead's critical path: at 0.92 the 1M x 128 search took
-    // 15% longer).  The distance cache (cleared when half full) gets at least
+    // 15% longer).  The distance cache (cleared when 5/8 full) gets at least
     // 56 buckets and grows into the slack of the last LDS granule (below).
     a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
     a.dc_buckets = 56;
