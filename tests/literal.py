@@ -1,21 +1,29 @@
 """Independent, deliberately naive re-derivations used to pin the oracle.
 
 Nothing here calls the oracle or the GPU library.  These are brute-force or
-literal forms of the paper's definitions, valid only for tiny inputs:
+restated forms of the paper's definitions, valid only for tiny inputs:
 
 * ``brute_knn``: linear scan (Sec. 1, Sec. 5.1 ground truth) with numpy,
   ties by id via lexsort.
 * ``all_bridges``: every one of the K^P concatenated bridge vectors written
   out explicitly (Sec. 4.1, Cartesian concatenation), with its distance to
   the query computed on the full vector, not from tables.
-* ``literal_search``: Alg. 1 with ONE unbounded main queue that holds
-  reference and bridge vectors together (Sec. 4.2: "the main queue consists
-  of only one bridge vector if available"), the bridge order taken from the
-  explicit sort of ``all_bridges``.  Strict budget, (distance, node id) ties.
+* ``literal_search``: the evaluation order of Alg. 1 (Sec. 4.2) stated as a
+  merge of two ordered streams.  Bridge vectors are consumed in the order of
+  an explicit sort of ``all_bridges``; reference vectors come from a
+  best-first frontier kept as a sorted list and cut back to its L best
+  after every insertion (L = None: no cut).  The next vertex expanded is
+  whichever stream's head is smaller in (distance, node id).  Holding every
+  bridge in the sorted stream expands the same vertices in the same order
+  as extracting one bridge at a time, because a bridge never precedes the
+  one before it.  Strict budget; (distance, node id) ties.
+* ``seeded_graph_search``: the neighborhood-graph search of Sec. 2.2 with no
+  bridge graph: fixed seed vectors are measured first, then the frontier is
+  expanded best first.
 """
 from __future__ import annotations
 
-import heapq
+import bisect
 import itertools
 
 import numpy as np
@@ -68,44 +76,84 @@ def bridge_order(q, codebooks):
     return [(int(l), float(D[l])) for l in order]
 
 
-def literal_search(X, codebooks, graph, bridge_lists, q, k, T):
-    """Alg. 1 with one unbounded priority queue over references and bridges.
-    bridge_lists: dict lid -> list of reference ids.  Returns (trace, ids, dists)."""
+def _expand_stream(X, graph, q, T, L, head_lists, bridge_stream, bridge_lists):
+    """Shared walk of the two streams.  head_lists: lists of ids measured
+    before anything else (the seeds of a graph search), in order."""
     n = len(X)
-    border = bridge_order(q, codebooks)
-    nxt = iter(border)
-    color = np.zeros(n, bool)
-    Qh = []
-    b = next(nxt, None)
-    if b is not None:
-        heapq.heappush(Qh, (b[1], n + b[0]))
-    t, trace, res = 0, [], []
-    while Qh and t < T:
-        D, node = heapq.heappop(Qh)
-        if node >= n:
-            adj = bridge_lists.get(node - n, [])
-        else:
-            adj = list(graph[node])
-        for x in adj:
-            if t == T:
-                break
+    seen = set()
+    trace, measured = [], []
+    frontier = []          # sorted (distance, id), at most L long
+    bi = 0
+
+    def visit(ids):
+        for x in ids:
+            if len(trace) == T:
+                return
             x = int(x)
-            if color[x]:
+            if x in seen:
                 continue
-            color[x] = True
-            dx = sqdist(q, X[x])
-            heapq.heappush(Qh, (dx, x))
-            res.append((dx, x))
+            seen.add(x)
+            key = (sqdist(q, X[x]), x)
             trace.append(x)
-            t += 1
-        if node >= n:
-            b = next(nxt, None)
-            if b is not None:
-                heapq.heappush(Qh, (b[1], n + b[0]))
-    res.sort()
-    ids = [x for _, x in res[:k]] + [-1] * max(0, k - len(res))
-    ds = [d for d, _ in res[:k]] + [np.inf] * max(0, k - len(res))
+            measured.append(key)
+            bisect.insort(frontier, key)
+            if L is not None and len(frontier) > L:
+                frontier.pop()           # the worst entry leaves (possibly the new one)
+
+    for ids in head_lists:
+        visit(ids)
+    while len(trace) < T:
+        nb = bridge_stream[bi] if bi < len(bridge_stream) else None
+        nf = frontier[0] if frontier else None
+        if nb is None and nf is None:
+            break
+        if nf is None or (nb is not None and (nb[1], n + nb[0]) < nf):
+            bi += 1
+            visit(bridge_lists.get(nb[0], []))
+        else:
+            frontier.pop(0)
+            visit(graph[nf[1]])
+    return trace, measured
+
+
+def _topk(measured, k):
+    best = sorted(measured)[:k]
+    ids = [x for _, x in best] + [-1] * max(0, k - len(best))
+    ds = [d for d, _ in best] + [np.inf] * max(0, k - len(best))
+    return ids, ds
+
+
+def literal_search(X, codebooks, graph, bridge_lists, q, k, T, L=None):
+    """Alg. 1 as a merge of the sorted bridge stream and a best-first frontier
+    of at most L references.  bridge_lists: dict lid -> list of reference ids.
+    Returns (trace, ids, dists)."""
+    trace, measured = _expand_stream(X, graph, q, T, L, [], bridge_order(q, codebooks), bridge_lists)
+    ids, ds = _topk(measured, k)
     return trace, ids, ds
+
+
+def seeded_graph_search(X, graph, seeds, q, k, T, L=None):
+    """Neighborhood-graph search without bridges (Sec. 2.2): the seeds are
+    measured in the given order, then the frontier is expanded best first."""
+    trace, measured = _expand_stream(X, graph, q, T, L, [seeds], [], {})
+    ids, ds = _topk(measured, k)
+    return trace, ids, ds
+
+
+def bf16_round(x):
+    """float32 -> nearest bfloat16 value (ties to an even last bit), as float64.
+    Written from the definition: bfloat16 keeps the top 16 bits of the float32
+    pattern; the two candidates are the patterns just below and just above."""
+    x = np.asarray(x, np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    lo = (u & 0xFFFF0000).astype(np.uint32).view(np.float32).astype(np.float64)
+    hi_bits = ((u & 0xFFFF0000) + 0x10000).astype(np.uint32)
+    hi = hi_bits.view(np.float32).astype(np.float64)
+    xv = x.astype(np.float64)
+    dlo, dhi = np.abs(xv - lo), np.abs(hi - xv)
+    lo_even = ((u >> 16) & 1) == 0
+    pick_lo = (dlo < dhi) | ((dlo == dhi) & lo_even)
+    return np.where(pick_lo, lo, hi)
 
 
 def csr_to_lists(off, ids):

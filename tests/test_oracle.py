@@ -112,8 +112,8 @@ def test_golden_search_cases():
             assert rid[0].tolist() == c["ids"], c
             assert rdist[0].tolist() == c["dists"], c
             assert [v for v in tr[0].tolist() if v >= 0] == c["trace"], c
-            # the literal single-queue form reproduces the same hand trace
-            ltr, lid_, ld = literal.literal_search(X, cb, G, gd["bridges"], q[0], c["k"], T)
+            # the two-stream form reproduces the same hand trace
+            ltr, lid_, ld = literal.literal_search(X, cb, G, gd["bridges"], q[0], c["k"], T, L=c["L"])
             assert ltr == c["trace"] and lid_ == c["ids"] and ld == c["dists"]
             ncase += 1
     assert ncase == 8
@@ -322,6 +322,44 @@ def test_search_matches_literal_single_queue(trial):
             assert [v for v in tr[i].tolist() if v >= 0] == ltr
             assert rid[i].tolist() == lid_
             assert rd[i].tolist() == ld
+
+
+@pytest.mark.parametrize("trial", range(10))
+def test_bounded_queue_matches_literal_eviction(trial):
+    """Reading 5 with L < T: a frontier cut back to its L best after each
+    insertion (the two-stream form) expands the same vertices in the same
+    order as the oracle's bounded queue with worst-eviction, on tie-heavy
+    and tie-free data, with every bridge rule."""
+    rng = np.random.default_rng(500 + trial)
+    P = 1 + trial % 3
+    hi = 4 if trial % 2 == 0 else 256
+    X, cb, g, off, ids = tiny_index(rng, n=90, d=6 if P == 3 else 8, P=P, K=3, R=4, hi=hi,
+                                    t=1 + (trial % 3), b=(trial % 4))
+    lists = literal.csr_to_lists(off, ids)
+    Q = tiny_u8(rng, 5, X.shape[1], hi=hi)
+    for L in (1, 2, 5, 17):
+        for T in (9, 40, 90):
+            rid, rd, tr = oracle.search(X, cb, g, off, ids, Q, 6, T, L, trace_len=T)
+            for i in range(len(Q)):
+                ltr, lid_, ld = literal.literal_search(X, cb, g, lists, Q[i], 6, T, L=L)
+                assert [v for v in tr[i].tolist() if v >= 0] == ltr, (L, T, i)
+                assert rid[i].tolist() == lid_
+                assert rd[i].tolist() == ld
+
+
+def test_bounded_queue_differs_from_unbounded():
+    """The bound is not vacuous: on these inputs a queue of L = 1 expands
+    other vertices than the unbounded queue (both forms agree on which)."""
+    rng = np.random.default_rng(42)
+    X, cb, g, off, ids = tiny_index(rng, n=120, d=8, P=2, K=3, R=4, hi=256, t=1, b=0)
+    lists = literal.csr_to_lists(off, ids)
+    Q = tiny_u8(rng, 6, 8)
+    differ = 0
+    for i in range(len(Q)):
+        a, _, _ = literal.literal_search(X, cb, g, lists, Q[i], 5, 60, L=1)
+        b, _, _ = literal.literal_search(X, cb, g, lists, Q[i], 5, 60)
+        differ += a != b
+    assert differ > 0
 
 
 def test_search_f32_matches_literal():
