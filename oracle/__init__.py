@@ -32,27 +32,34 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def load(path: str):
+    """Open a compiled oracle library and declare its functions."""
+    L = C.CDLL(path)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int
+    L.orc_knn.argtypes = [vp, i64, i32, i32, vp, i64, vp, i32, vp, vp]
+    L.orc_splitmix64.argtypes = [C.c_uint64, i64, vp]
+    L.orc_init_rows.argtypes = [i64, i32, C.c_uint64, vp]
+    L.orc_kmeans.argtypes = [vp, i64, i32, i32, i32, i32, i32, C.c_uint64, vp, vp]
+    L.orc_tables.argtypes = [vp, i32, i32, i32, i32, vp, vp]
+    L.orc_sort_tables.argtypes = [i32, i32, vp, vp, vp]
+    L.orc_mseq.argtypes = [i32, i32, vp, i64, vp, vp, vp]
+    L.orc_mseq.restype = i64
+    L.orc_bridge_graph.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp, i64]
+    L.orc_bridge_graph.restype = i64
+    L.orc_search.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp, i64,
+                             vp, vp, i32, i32, vp, vp, vp, i32, vp]
+    L.orc_search_ex.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp, i64,
+                                vp, vp, i32, i32, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
+    L.orc_bf16_round.argtypes = [vp, i64, vp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
-        vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int, C.c_double
-        L.orc_knn.argtypes = [vp, i64, i32, i32, vp, i64, vp, i32, vp, vp]
-        L.orc_splitmix64.argtypes = [C.c_uint64, i64, vp]
-        L.orc_init_rows.argtypes = [i64, i32, C.c_uint64, vp]
-        L.orc_kmeans.argtypes = [vp, i64, i32, i32, i32, i32, i32, C.c_uint64, vp, vp]
-        L.orc_tables.argtypes = [vp, i32, i32, i32, i32, vp, vp]
-        L.orc_sort_tables.argtypes = [i32, i32, vp, vp, vp]
-        L.orc_mseq.argtypes = [i32, i32, vp, i64, vp, vp, vp]
-        L.orc_mseq.restype = i64
-        L.orc_bridge_graph.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, i32, vp, vp, vp, i64]
-        L.orc_bridge_graph.restype = i64
-        L.orc_search.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp, i64,
-                                 vp, vp, i32, i32, vp, vp, vp, i32, vp]
-        _ = dbl
-        _lib = L
+        _lib = load(LIB)
     return _lib
 
 
@@ -158,8 +165,20 @@ def bridge_graph(X: np.ndarray, codebooks: np.ndarray, t: int, b: int):
     return off, ids[:e].copy(), bd[:e].copy()
 
 
-def search(X, codebooks, graph, off, ids, Q, k, T, L, trace_len: int = 0, stats: bool = False):
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Nearest bfloat16 value of each float32 (ties to an even last bit), as float64."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty(x.shape, np.float64)
+    lib().orc_bf16_round(_p(x), x.size, _p(out))
+    return out
+
+
+def search(X, codebooks, graph, off, ids, Q, k, T, L, trace_len: int = 0, stats: bool = False,
+           precision: int = 0, rerank_k: int = 0, seeds=None):
     """Alg. 1 on the given index.  k and T may be scalars or per-query arrays.
+    precision 1 (float data): bfloat16 rows drive the search, the best
+    max(k, rerank_k) are re-ranked on the float rows.  seeds (array of ids):
+    the graph search without bridges, the seeds measured first.
     Returns (ids int32 nq x kmax, dists float64 nq x kmax[, trace][, stats])."""
     X = np.ascontiguousarray(X)
     n, d = X.shape
@@ -181,8 +200,10 @@ def search(X, codebooks, graph, off, ids, Q, k, T, L, trace_len: int = 0, stats:
     od = np.empty((nq, kmax), np.float64)
     tr = np.empty((nq, trace_len), np.int32) if trace_len > 0 else None
     st = np.empty((nq, 6), np.int64) if stats else None
-    lib().orc_search(_p(X), n, d, _dt(X), P, K, _p(np.ascontiguousarray(codebooks)), R, _p(graph), _p(off),
-                     _p(ids_), _p(Q), nq, _p(ks), _p(Ts), kmax, L, _p(oid), _p(od), _p(tr), trace_len, _p(st))
+    sd = None if seeds is None else np.ascontiguousarray(seeds, dtype=np.uint32)
+    lib().orc_search_ex(_p(X), n, d, _dt(X), P, K, _p(np.ascontiguousarray(codebooks)), R, _p(graph), _p(off),
+                        _p(ids_), _p(Q), nq, _p(ks), _p(Ts), kmax, L, precision, rerank_k, 1 if sd is None else 0,
+                        _p(sd), 0 if sd is None else len(sd), _p(oid), _p(od), _p(tr), trace_len, _p(st))
     out = [oid, od]
     if tr is not None:
         out.append(tr)

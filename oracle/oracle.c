@@ -93,6 +93,42 @@ static double sqdist_rows(const void* A, int64_t ra, const void* B, int64_t rb, 
 }
 
 /* ------------------------------------------------------------------ */
+/* bfloat16 (precision form of the search for float data).  A bfloat16  */
+/* keeps the sign, the 8 exponent bits and the top 7 fraction bits of a */
+/* float32.  The value nearest to f is one of the two patterns around   */
+/* it: f cut toward zero to 16 bits, or the next one away from zero.     */
+/* The nearer one is taken; at equal distance the one whose last kept   */
+/* bit is 0.  Inputs are finite.                                        */
+/* ------------------------------------------------------------------ */
+static double bf16_nearest(float f) {
+    uint32_t u, toward, away;
+    float ft, fa;
+    memcpy(&u, &f, 4);
+    toward = u & 0xFFFF0000u;
+    away = toward + 0x10000u;
+    memcpy(&ft, &toward, 4);
+    memcpy(&fa, &away, 4);
+    double et = fabs((double)f - (double)ft), ea = fabs((double)fa - (double)f);
+    if (et < ea) return (double)ft;
+    if (ea < et) return (double)fa;
+    return ((toward >> 16) & 1u) ? (double)fa : (double)ft;
+}
+
+void orc_bf16_round(const float* x, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; i++) out[i] = bf16_nearest(x[i]);
+}
+
+/* squared distance from a float query to the bfloat16 copy of a float row */
+static double sqdist_f32_bf16(const float* q, const float* x, int len) {
+    double s = 0.0;
+    for (int i = 0; i < len; i++) {
+        double t = (double)q[i] - bf16_nearest(x[i]);
+        s += t * t;
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
 /* Bounded set of the best keys: keeps the `cap` smallest keys offered. */
 /* Plain unsorted array; every operation scans it.                     */
 /* ------------------------------------------------------------------ */
@@ -517,12 +553,25 @@ done:
 /* trace (optional, nq x tmax): the reference ids in evaluation order.  */
 /* stats (optional, nq x 6): evaluations, reference pops, bridge pops,  */
 /* bridge-list entries read, adjacency entries read, max heap size.     */
+/*                                                                      */
+/* Two further forms (orc_search_ex):                                    */
+/*  precision 1 (float data only): every distance that drives the       */
+/*    search is taken from the bfloat16 copies of the rows (the query    */
+/*    stays float); the result set keeps max(k, rerank_k) candidates     */
+/*    (rerank_k = 0: k), whose distances are then measured again on the */
+/*    float rows and sorted by (D, id); the first k are returned.        */
+/*  use_bridges 0: the neighborhood-graph search of Sec. 2.2 without a   */
+/*    bridge graph.  The nseeds seed vectors are measured first, in the  */
+/*    given order, like the adjacency list of a vertex expanded before   */
+/*    anything else; then the main queue is expanded best first.        */
 /* ------------------------------------------------------------------ */
-void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const void* codebooks, int R,
-                const uint32_t* G, const uint32_t* off, const uint32_t* ids, const void* Qv, int64_t nq,
-                const int32_t* ks, const int32_t* Ts, int kmax, int L, int32_t* out_ids, double* out_d,
-                int32_t* trace, int tmax, int64_t* stats) {
+void orc_search_ex(const void* X, int64_t n, int d, int dtype, int P, int K, const void* codebooks, int R,
+                   const uint32_t* G, const uint32_t* off, const uint32_t* ids, const void* Qv, int64_t nq,
+                   const int32_t* ks, const int32_t* Ts, int kmax, int L, int precision, int rerank_k,
+                   int use_bridges, const uint32_t* seeds, int nseeds, int32_t* out_ids, double* out_d,
+                   int32_t* trace, int tmax, int64_t* stats) {
     const size_t esz = dtype == ORC_U8 ? 1 : 4;
+    const int bf16 = dtype == ORC_F32 && precision == 1;
     unsigned char* color = (unsigned char*)calloc((size_t)n, 1); /* 0 = white, 1 = black */
     int64_t* touched = NULL;
     int64_t touched_cap = 0;
@@ -530,32 +579,53 @@ void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const 
     int32_t* perm = (int32_t*)malloc(sizeof(int32_t) * (size_t)P * K);
     double* val = (double*)malloc(sizeof(double) * (size_t)P * K);
     okey_t* qbuf = (okey_t*)malloc(sizeof(okey_t) * (size_t)(L > 0 ? L : 1));
-    okey_t* rbuf = (okey_t*)malloc(sizeof(okey_t) * (size_t)(kmax > 0 ? kmax : 1));
+    int rmax = kmax > rerank_k ? kmax : rerank_k;
+    okey_t* rbuf = (okey_t*)malloc(sizeof(okey_t) * (size_t)(rmax > 0 ? rmax : 1));
 
     for (int64_t qi = 0; qi < nq; qi++) {
         const int k = ks[qi], T = Ts[qi];
+        const int rcap = bf16 && rerank_k > k ? rerank_k : k;
         const char* q = (const char*)Qv + (size_t)qi * d * esz;
         int64_t st_eval = 0, st_rpop = 0, st_bpop = 0, st_blist = 0, st_adj = 0;
         if (touched_cap < T) {
             touched_cap = T;
             touched = (int64_t*)realloc(touched, sizeof(int64_t) * (size_t)touched_cap);
         }
-        /* query preprocessing: tables and per-subspace sort (Sec. 4.2) */
-        orc_tables(q, d, dtype, P, K, codebooks, tab);
-        orc_sort_tables(P, K, tab, perm, val);
         mseq_t ms;
-        mseq_init(&ms, P, K, perm, val);
-
-        bset_t Qs = {qbuf, 0, L};
-        bset_t Rs = {rbuf, 0, k};
+        int have_bridge = 0;
         int64_t blid = 0;
         double bsum = 0.0;
-        int have_bridge = mseq_next(&ms, &blid, &bsum); /* nearest bridge vector */
-        int64_t t = 0;
+        if (use_bridges) {
+            /* query preprocessing: tables and per-subspace sort (Sec. 4.2) */
+            orc_tables(q, d, dtype, P, K, codebooks, tab);
+            orc_sort_tables(P, K, tab, perm, val);
+            mseq_init(&ms, P, K, perm, val);
+            have_bridge = mseq_next(&ms, &blid, &bsum); /* nearest bridge vector */
+        }
 
-        while (t < T) {
-            const uint32_t* adj;
-            int64_t alen;
+        bset_t Qs = {qbuf, 0, L};
+        bset_t Rs = {rbuf, 0, rcap};
+        int64_t t = 0;
+        /* the seeds of a graph search are measured before anything else */
+        const uint32_t* adj = use_bridges ? NULL : seeds;
+        int64_t alen = use_bridges ? 0 : nseeds;
+
+        for (;;) {
+            for (int64_t a = 0; a < alen; a++) {
+                if (t == T) break;
+                int64_t x = adj[a];
+                if (color[x]) continue;
+                color[x] = 1;
+                touched[t] = x;
+                double dx = bf16 ? sqdist_f32_bf16((const float*)q, (const float*)X + x * d, d)
+                                 : sqdist_rows(q, 0, X, x, d, 0, d, dtype);
+                okey_t c = {dx, x};
+                if (trace && t < tmax) trace[qi * tmax + t] = (int32_t)x;
+                t++;
+                bset_offer(&Rs, c);
+                bset_offer(&Qs, c);
+            }
+            if (t >= T) break;
             okey_t bkey = {bsum, n + blid};
             if (have_bridge && (Qs.n == 0 || key_less(bkey, Qs.e[bset_argmin(&Qs)]))) {
                 /* the top of the main queue is the bridge vector */
@@ -573,24 +643,16 @@ void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const 
                 break; /* queue empty and every bridge vector consumed */
             }
             st_adj += alen;
-            for (int64_t a = 0; a < alen; a++) {
-                if (t == T) break;
-                int64_t x = adj[a];
-                if (color[x]) continue;
-                color[x] = 1;
-                touched[t] = x;
-                okey_t c = {sqdist_rows(q, 0, X, x, d, 0, d, dtype), x};
-                if (trace && t < tmax) trace[qi * tmax + t] = (int32_t)x;
-                t++;
-                bset_offer(&Rs, c);
-                bset_offer(&Qs, c);
-            }
         }
+        if (bf16) /* the kept candidates measured again on the float rows */
+            for (int i = 0; i < Rs.n; i++)
+                Rs.e[i].d = sqdist_rows(q, 0, X, Rs.e[i].id, d, 0, d, dtype);
         /* results ascending by (D, id), padded */
         qsort(Rs.e, (size_t)Rs.n, sizeof(okey_t), key_cmp_qsort);
         for (int i = 0; i < kmax; i++) {
-            out_ids[qi * kmax + i] = i < Rs.n ? (int32_t)Rs.e[i].id : -1;
-            out_d[qi * kmax + i] = i < Rs.n ? Rs.e[i].d : INFINITY;
+            int have = i < Rs.n && i < k;
+            out_ids[qi * kmax + i] = have ? (int32_t)Rs.e[i].id : -1;
+            out_d[qi * kmax + i] = have ? Rs.e[i].d : INFINITY;
         }
         if (trace)
             for (int64_t i = t; i < tmax; i++) trace[qi * tmax + i] = -1;
@@ -601,11 +663,11 @@ void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const 
             stats[qi * 6 + 2] = st_bpop;
             stats[qi * 6 + 3] = st_blist;
             stats[qi * 6 + 4] = st_adj;
-            stats[qi * 6 + 5] = ms.max_size;
+            stats[qi * 6 + 5] = use_bridges ? ms.max_size : 0;
         }
         /* every vector white again for the next query */
         for (int64_t i = 0; i < t; i++) color[touched[i]] = 0;
-        mseq_free(&ms);
+        if (use_bridges) mseq_free(&ms);
     }
     free(color);
     free(touched);
@@ -614,4 +676,12 @@ void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const 
     free(val);
     free(qbuf);
     free(rbuf);
+}
+
+void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const void* codebooks, int R,
+                const uint32_t* G, const uint32_t* off, const uint32_t* ids, const void* Qv, int64_t nq,
+                const int32_t* ks, const int32_t* Ts, int kmax, int L, int32_t* out_ids, double* out_d,
+                int32_t* trace, int tmax, int64_t* stats) {
+    orc_search_ex(X, n, d, dtype, P, K, codebooks, R, G, off, ids, Qv, nq, ks, Ts, kmax, L, 0, 0, 1, NULL, 0,
+                  out_ids, out_d, trace, tmax, stats);
 }

@@ -446,3 +446,99 @@ def test_degenerate_inputs():
     rid, rd = oracle.search(X1, cb1, np.zeros((1, 0), np.uint32), off1, ids1,
                             np.array([[0, 0]], np.uint8), 2, 5, 4)
     assert rid.tolist() == [[0, -1]] and rd[0, 0] == 130.0
+
+
+# ---------------------------------------------------------------- bf16 precision form
+
+def test_bf16_rounding_matches_library_conversion():
+    """The oracle's bfloat16 rounding against torch's float32 -> bfloat16
+    conversion (round to nearest even), including exact halfway cases."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(40)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-6, 6, 20000),
+                        np.abs(rng.standard_normal(5000))]).astype(np.float32)
+    # halfway between two bfloat16 values: low 16 bits exactly 0x8000
+    half = (rng.integers(0x3F000000, 0x41000000, 4000, dtype=np.uint64) & ~np.uint64(0xFFFF)) | np.uint64(0x8000)
+    x = np.concatenate([x, half.astype(np.uint32).view(np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(oracle.bf16_round(x), ref)
+    np.testing.assert_array_equal(literal.bf16_round(x), ref)
+
+
+def _f32_index(rng, n=120, d=8, P=2, K=3, R=4, t=2, b=3):
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    cb = oracle.kmeans(X, P, K, 3, 5)
+    g, _ = oracle.knn_graph_rows(X, np.arange(n), R)
+    off, ids, _ = oracle.bridge_graph(X, cb, t, b)
+    return X, cb, g.astype(np.uint32), off, ids
+
+
+@pytest.mark.parametrize("rerank_k", [0, 3, 12])
+def test_bf16_search_is_exact_search_on_rounded_rows_then_rerank(rerank_k):
+    """Precision form: the traversal equals the two-stream search run on the
+    bfloat16-rounded rows (float query), and the answer is the best
+    max(k, rerank_k) of what it measured, measured again on the float rows."""
+    rng = np.random.default_rng(41 + rerank_k)
+    X, cb, g, off, ids = _f32_index(rng)
+    lists = literal.csr_to_lists(off, ids)
+    Q = rng.standard_normal((6, 8)).astype(np.float32)
+    Xb = literal.bf16_round(X)
+    k = 4
+    for L, T in ((64, 50), (3, 80)):
+        rid, rd, tr = oracle.search(X, cb, g, off, ids, Q, k, T, L, trace_len=T, precision=1, rerank_k=rerank_k)
+        for i in range(len(Q)):
+            ltr, _, _ = literal.literal_search(Xb, cb, g, lists, Q[i], k, T, L=L)
+            assert [v for v in tr[i].tolist() if v >= 0] == ltr
+            approx = sorted((literal.sqdist(Q[i], Xb[x]), x) for x in ltr)[:max(k, rerank_k)]
+            exact = sorted((literal.sqdist(Q[i], X[x]), x) for _, x in approx)[:k]
+            assert rid[i].tolist() == [x for _, x in exact]
+            np.testing.assert_allclose(rd[i], [dd for dd, _ in exact], rtol=1e-12)
+
+
+def test_bf16_search_on_representable_rows_equals_exact_search():
+    """Rows whose values are bfloat16 numbers already: both precisions agree."""
+    rng = np.random.default_rng(43)
+    X = rng.integers(-50, 50, size=(100, 8)).astype(np.float32) / 4
+    cb = oracle.kmeans(X, 2, 3, 3, 5)
+    g, _ = oracle.knn_graph_rows(X, np.arange(100), 4)
+    off, ids, _ = oracle.bridge_graph(X, cb, 2, 3)
+    Q = rng.standard_normal((5, 8)).astype(np.float32)
+    a = oracle.search(X, cb, g.astype(np.uint32), off, ids, Q, 5, 60, 8, trace_len=60)
+    b = oracle.search(X, cb, g.astype(np.uint32), off, ids, Q, 5, 60, 8, trace_len=60, precision=1)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+# ---------------------------------------------------------------- graph search without bridges (Sec. 2.2)
+
+@pytest.mark.parametrize("trial", range(6))
+def test_seeded_graph_search_matches_literal(trial):
+    rng = np.random.default_rng(600 + trial)
+    hi = 4 if trial % 2 == 0 else 256
+    X, cb, g, off, ids = tiny_index(rng, n=100, d=8, P=2, K=3, R=3 + trial % 3, hi=hi)
+    Q = tiny_u8(rng, 5, 8, hi=hi)
+    seeds = rng.choice(100, size=1 + trial * 2, replace=False).astype(np.uint32)
+    if trial == 3:
+        seeds = np.concatenate([seeds, seeds[:2]])        # repeated seeds are measured once
+    for L, T in ((64, 70), (2, 40), (7, 100)):
+        rid, rd, tr = oracle.search(X, cb, g, off, ids, Q, 5, T, L, trace_len=T, seeds=seeds)
+        for i in range(len(Q)):
+            ltr, lid_, ld = literal.seeded_graph_search(X, g, seeds, Q[i], 5, T, L=L)
+            assert [v for v in tr[i].tolist() if v >= 0] == ltr
+            assert rid[i].tolist() == lid_ and rd[i].tolist() == ld
+
+
+def test_seeded_graph_search_closed_forms():
+    rng = np.random.default_rng(44)
+    X, cb, g, off, ids = tiny_index(rng, n=80, d=8, P=2, K=3, R=3, hi=256)
+    Q = tiny_u8(rng, 4, 8)
+    # no graph edges: exactly the seeds, in order, up to the budget
+    seeds = np.array([5, 9, 2, 77, 40], np.uint32)
+    _, _, tr = oracle.search(X, cb, np.zeros((80, 0), np.uint32), off, ids, Q, 3, 4, 64, trace_len=4, seeds=seeds)
+    assert (tr == seeds[:4]).all()
+    # every vector a seed and T >= n: the exact nearest neighbours
+    allseeds = rng.permutation(80).astype(np.uint32)
+    rid, rd = oracle.search(X, cb, g, off, ids, Q, 10, 80, 64, seeds=allseeds)
+    eid, ed = literal.brute_knn(X, Q, 10)
+    np.testing.assert_array_equal(rid, eid)
+    np.testing.assert_array_equal(rd, ed)
