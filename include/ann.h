@@ -271,6 +271,24 @@ int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq
                          int64_t workspace_bytes, void* stream);
 
 /*
+ * Neighborhood-graph search without the bridge graph (Sec. 2.2, the
+ * iterative search that Sec. 5.3 compares against): the seed vectors are
+ * measured first, in the given order (a repeated seed is measured once),
+ * then the main queue is expanded best first over the kNN graph exactly as
+ * in Alg. 1, with no bridge vector ever in the queue.  The budget counts
+ * the seeds' distance evaluations too.
+ *  d_seeds  device, n_seeds int32 reference ids in [0, n), the same for every
+ *           query (an id outside [0, n) is skipped); 0 <= n_seeds <= 2^20.
+ * Other arguments as ann_search_device (one k and budget for the batch;
+ * exact precision only).  In d_stats the seed list counts as one bridge pop
+ * of n_seeds entries.  Asynchronous on `stream`.
+ * Errors: ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE.
+ */
+int ann_search_graph_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                            const int32_t* d_seeds, int32_t n_seeds, const ann_search_params* params,
+                            int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
+
+/*
  * Launch autotuner: times the launch-tuning choices of ann_search_params
  * (lookahead, persistent, waves_per_cu, order) on the given device batch
  * and writes the fastest into *params; the other fields are kept.  Every

@@ -61,6 +61,8 @@ SIGNATURES = {
     "ann_search_workspace_size": (_i32, [_vp, _i64, _i32, _i32, C.POINTER(SearchParams), C.POINTER(_i64)]),
     "ann_search_device_ws": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp, _vp, _vp,
                                     _vp, _vp, _i64, _vp]),
+    "ann_search_graph_device": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _i32, C.POINTER(SearchParams), _vp, _vp,
+                                       _vp, _vp, _vp]),
     "ann_autotune": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp]),
     "ann_query_tables_device": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "ann_knn_device": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),

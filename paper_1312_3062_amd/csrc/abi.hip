@@ -427,6 +427,24 @@ static SearchLaunch make_launch(const ann_index* idx, const void* d_queries, int
     return a;
 }
 
+}  // extern "C"
+
+namespace ann {
+// Smallest workspace ann_search_device_ws accepts for this request: the
+// per-query lists plus one global multi-sequence slot.  Arguments are
+// checked as ann_search_device checks them.
+int search_min_workspace(const ann_index* idx, int64_t nq, int32_t k, int32_t budget, const ann_search_params* sp,
+                         int64_t* bytes) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    return search_workspace_bytes(
+        make_launch(idx, nullptr, nq, k, budget, nullptr, nullptr, sp, nullptr, nullptr, nullptr, nullptr, nullptr),
+        bytes, true);
+}
+}  // namespace ann
+
+extern "C" {
+
 int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
                       const int32_t* d_k, const int32_t* d_budget, const ann_search_params* sp, int32_t* d_ids,
                       void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream) {
@@ -460,6 +478,25 @@ int ann_search_device_ws(const ann_index* idx, const void* d_queries, int64_t nq
         make_launch(idx, d_queries, nq, k, budget, d_k, d_budget, sp, d_ids, d_dists, d_stats, d_trace, stream);
     a.workspace = workspace;
     a.workspace_bytes = workspace_bytes;
+    return launch_search(a);
+}
+
+int ann_search_graph_device(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                            const int32_t* d_seeds, int32_t n_seeds, const ann_search_params* sp, int32_t* d_ids,
+                            void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream) {
+    int rc = check_search(idx, nq, k, budget, sp);
+    if (rc) return rc;
+    ANN_REQUIRE(nq == 0 || (d_queries && d_ids && d_dists), "search: null device buffer");
+    ANN_REQUIRE(n_seeds >= 0 && n_seeds <= (1 << 20), "ann_search_graph_device: n_seeds must be in [0, 2^20]");
+    ANN_REQUIRE(n_seeds == 0 || d_seeds, "ann_search_graph_device: null seeds");
+    ANN_REQUIRE(!sp || sp->precision == ANN_PRECISION_EXACT || idx->dtype == ANN_U8,
+                "ann_search_graph_device: exact precision only");
+    SearchLaunch a =
+        make_launch(idx, d_queries, nq, k, budget, nullptr, nullptr, sp, d_ids, d_dists, d_stats, d_trace, stream);
+    a.precision = ANN_PRECISION_EXACT;
+    a.graph_only = true;
+    a.d_seeds = reinterpret_cast<const uint32_t*>(d_seeds);
+    a.n_seeds = n_seeds;
     return launch_search(a);
 }
 

@@ -44,11 +44,17 @@ struct SearchLaunch {
     int waves_per_cu = 0;   // persistent: resident workgroups per CU (0: all that fit)
     int order = 0;          // persistent with per-query budgets: longest first
     void* workspace = nullptr;  // caller-provided workspace (null: allocated on the stream)
+    // neighborhood-graph search without bridges: seed ids measured first
+    bool graph_only = false;
+    const uint32_t* d_seeds = nullptr;
+    int n_seeds = 0;
     int64_t workspace_bytes = 0;
 };
 
 int launch_search(const SearchLaunch& a);
-int search_workspace_bytes(const SearchLaunch& a, int64_t* bytes);
+int search_workspace_bytes(const SearchLaunch& a, int64_t* bytes, bool minimum = false);
+int search_min_workspace(const ann_index* idx, int64_t nq, int32_t k, int32_t budget, const ann_search_params* sp,
+                         int64_t* bytes);
 int launch_tables(const ann_index* idx, const void* d_q, int64_t nq, void* d_sorted, int32_t* d_perm,
                   hipStream_t s);
 int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, int64_t nq, int k, int exclude_self,

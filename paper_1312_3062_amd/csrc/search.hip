@@ -82,6 +82,9 @@ struct SearchArgs {
     int Tall;                // largest budget of the whole request: clamp and trace row stride
     uint32_t* work_counter;  // persistent launch: next work item (null: grid-stride)
     const uint32_t* perm;    // optional serving order of the queries
+    int graph_only;          // neighborhood-graph search without bridges
+    const uint32_t* seeds;   // its seed ids, measured first
+    int nseeds;
     // LDS layout (byte offsets)
     int o_mrg;  // merge buffer of the register queues
     int o_q, o_sv, o_perm, o_ms, o_rk, o_ro, o_rl, o_sk, o_pid, o_pd, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd,
@@ -747,7 +750,8 @@ k_search(SearchArgs a) {
 
         // ---- tables and their sort (the raw tables use the visited set's
         //      memory, cleared afterwards); the nearest bridge seeds the frontier
-        compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, H, sv, perm, lane);
+        const bool graph_only = a.graph_only != 0;  // neighborhood-graph search, no bridges
+        if (!graph_only) compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, H, sv, perm, lane);
         for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
         __syncthreads();
         int slot = -1;  // global slot the enumeration moved to (main kernel)
@@ -766,14 +770,27 @@ k_search(SearchArgs a) {
             return mseq_conf(sv, perm, P, K, uint32_t(n), m);
         };
         PairMSeq<FLOAT> ms;
-        if (lane == 0) ms.init(ms_conf());
-        bool ms_alive = true;  // the enumeration can still yield bridges
+        if (lane == 0 && !graph_only) ms.init(ms_conf());
+        bool ms_alive = !graph_only;  // the enumeration can still yield bridges
         int heap_max = 1;
         int flags = 0;
         int ring_h = 0, ring_n = 0;
         int refills = 0;
         uint32_t ids_mask = 0, dist_mask = 0;  // ring entries with prefetched ids / distances
         uint64_t bkey = KEY_EMPTY;  // next non-empty bridge (ring head)
+        if (graph_only && a.nseeds > 0) {
+            // the seed list is expanded before anything else, like the list
+            // of a bridge at distance 0 walked from memory (key 0 is below
+            // every queue key); no bridge follows it
+            if (lane == 0) {
+                ring_key[0] = 0;
+                ring_off[0] = 0;
+                ring_len[0] = uint32_t(a.nseeds);
+            }
+            __syncthreads();
+            ring_n = 1;
+            bkey = 0;
+        }
         uint64_t Qv[1] = {KEY_EMPTY};
         int qn = 0;
         uint64_t Rv[KPL];
@@ -1094,9 +1111,11 @@ k_search(SearchArgs a) {
                 // the one that ends the list or the budget is merged here, that
                 // one below
                 flush(full);
+                const uint32_t* list = graph_only ? a.seeds : a.bids;
                 for (int c0 = 0;; c0 += WAVE) {
                     const int j = c0 + lane;
-                    id = j < len ? a.bids[base + j] : ID_EMPTY;
+                    id = j < len ? list[base + j] : ID_EMPTY;
+                    if (id >= uint32_t(n)) id = ID_EMPTY;  // a seed outside [0, n) is skipped
                     bool white = false;
                     if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
                     const uint64_t wm = __ballot(white);
@@ -1404,11 +1423,14 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.t_lo = 0;
     a.t_hi = s.Tmax;
     a.L = s.L;
-    a.rerank_k = s.rerank_k > 0 ? s.rerank_k : s.kmax;
+    a.rerank_k = s.rerank_k;  // 0: each query's own k
     a.out_ids = s.d_ids;
     a.out_d = s.d_dists;
     a.stats = s.d_stats;
     a.trace = s.d_trace;
+    a.graph_only = s.graph_only ? 1 : 0;
+    a.seeds = s.d_seeds;
+    a.nseeds = s.graph_only ? s.n_seeds : 0;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
     // than it evaluates); buckets for a final load of about 0.8 (its lookups
@@ -1486,26 +1508,46 @@ struct ClassPlan {
     int t_lo, t_hi;
 };
 
-static int make_class_plans(const SearchLaunch& s, std::vector<ClassPlan>& out) {
-    out.clear();
-    std::vector<std::pair<int, int>> ranges;
+// at most three classes, held in place (a search launch allocates nothing on
+// the host either)
+struct ClassPlans {
+    ClassPlan c[3];
+    int n = 0;
+    ClassPlan* begin() { return c; }
+    ClassPlan* end() { return c + n; }
+    const ClassPlan* begin() const { return c; }
+    const ClassPlan* end() const { return c + n; }
+};
+
+static int make_class_plans(const SearchLaunch& s, ClassPlans& out) {
+    out.n = 0;
+    int ranges[3][2];
+    int nr = 0;
     if (!s.d_T || s.Tmax <= 512) {
-        ranges.push_back({0, s.Tmax});
+        ranges[nr][0] = 0;
+        ranges[nr++][1] = s.Tmax;
     } else {
-        if (s.Tmax > 2048) ranges.push_back({2049, s.Tmax});
-        ranges.push_back({513, std::min(s.Tmax, 2048)});
-        ranges.push_back({0, 512});
+        if (s.Tmax > 2048) {
+            ranges[nr][0] = 2049;
+            ranges[nr++][1] = s.Tmax;
+        }
+        ranges[nr][0] = 513;
+        ranges[nr++][1] = std::min(s.Tmax, 2048);
+        ranges[nr][0] = 0;
+        ranges[nr++][1] = 512;
     }
-    for (auto r : ranges) {
+    for (int i = 0; i < nr; ++i) {
         SearchLaunch sc = s;
-        sc.Tmax = r.second;
-        ClassPlan c;
+        sc.Tmax = ranges[i][1];
+        ClassPlan& c = out.c[out.n];
         int rc = make_plan(sc, c.pl);
         if (rc) return rc;
         c.pl.a.Tall = c.pl.a2.Tall = s.Tmax;
-        c.pl.a.t_lo = c.pl.a2.t_lo = r.first;
-        c.pl.a.t_hi = c.pl.a2.t_hi = r.second;
-        out.push_back(c);
+        c.pl.a.t_lo = c.pl.a2.t_lo = ranges[i][0];
+        c.pl.a.t_hi = c.pl.a2.t_hi = ranges[i][1];
+        c.t_lo = ranges[i][0];
+        c.t_hi = ranges[i][1];
+        ++out.n;
     }
     return ANN_OK;
 }
@@ -1517,10 +1559,10 @@ struct WsLayout {
     size_t slot_bytes = 0, fixed = 0, total = 0;
 };
 
-static WsLayout ws_layout(const std::vector<ClassPlan>& cl, int64_t nq) {
+static WsLayout ws_layout(const ClassPlans& cl, int64_t nq) {
     WsLayout L;
     for (const auto& c : cl) L.max_slots = std::max(L.max_slots, c.pl.max_slots);
-    L.slot_bytes = cl.front().pl.slot_bytes;
+    L.slot_bytes = cl.c[0].pl.slot_bytes;
     L.bit_words = int(ceil_div(L.max_slots, 32));
     L.fixed = (256 + round16(size_t(L.bit_words) * 4) + round16(size_t(nq) * 4) + 256 + round16(size_t(nq) * 4) + 63) &
               ~size_t(63);
@@ -1528,17 +1570,18 @@ static WsLayout ws_layout(const std::vector<ClassPlan>& cl, int64_t nq) {
     return L;
 }
 
-int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes) {
-    std::vector<ClassPlan> cl;
+int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes, bool minimum) {
+    ClassPlans cl;
     int rc = make_class_plans(s, cl);
     if (rc) return rc;
-    *bytes = int64_t(ws_layout(cl, s.nq).total);
+    const WsLayout L = ws_layout(cl, s.nq);
+    *bytes = int64_t(minimum ? L.fixed + L.slot_bytes : L.total);
     return ANN_OK;
 }
 
 int launch_search(const SearchLaunch& s) {
     if (s.nq == 0) return ANN_OK;
-    std::vector<ClassPlan> cl;
+    ClassPlans cl;
     int rc = make_class_plans(s, cl);
     if (rc) return rc;
     const WsLayout L = ws_layout(cl, s.nq);

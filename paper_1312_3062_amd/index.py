@@ -178,6 +178,26 @@ class Index:
                                              _tptr(workspace), workspace.numel(), _stream_ptr(stream)))
         return ids, dd
 
+    def search_graph_device(self, queries, k: int, budget: int, seeds, queue_len: int = 64, out=None, stats=None,
+                            trace=None, stream=None, tune: Optional[dict] = None):
+        """Neighborhood-graph search without bridges (Sec. 2.2): `seeds` (int32
+        device tensor of reference ids) are measured first, then the kNN graph
+        is expanded best first.  Returns (ids, dists) tensors nq x k."""
+        import torch
+        nq = queries.shape[0]
+        dev = queries.device
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            dd = torch.empty((nq, k), dtype=torch.int32 if queries.dtype == torch.uint8 else torch.float32,
+                             device=dev)
+        else:
+            ids, dd = out
+        sp = search_params(queue_len, 0, 0, tune)
+        check(lib().ann_search_graph_device(self._h, _tptr(queries), nq, k, budget, _tptr(seeds), seeds.numel(),
+                                            C.byref(sp), _tptr(ids), _tptr(dd), _tptr(stats), _tptr(trace),
+                                            _stream_ptr(stream)))
+        return ids, dd
+
     def workspace_bytes(self, nq: int, k: int, budget: int, queue_len: int = 64, precision: int = 0,
                         rerank_k: int = 0, tune: Optional[dict] = None) -> int:
         sp = search_params(queue_len, precision, rerank_k, tune)

@@ -396,3 +396,151 @@ def test_empty_batch_and_zero_budget(tiny):
     assert ids.shape == (0, 10) and dd.shape == (0, 10)
     gi, gd = gpu_search(idx, tiny["Q"][:5], 7, 0, 64)
     assert (gi == -1).all() and (gd == 2147483647).all()
+
+
+# ---------------------------------------------------------------- bf16 gather against the oracle's bf16 form
+
+@pytest.mark.parametrize("rerank_k", [0, 20])
+def test_bf16_search_against_the_oracle_bf16_form(rerank_k):
+    """The bf16 traversal (bf16 rows, fp32 query and accumulation) against the
+    oracle's bf16 form (the same rows, rounded to nearest even, in fp64),
+    then the fp32 re-rank: ids equal on this small GIST-shaped index, returned
+    distances within 1e-4 relative of fp64 and of the oracle's."""
+    w = synth.scaled(synth.WORKLOADS["gist_like_1m_f32"], 4000, nq=60, K=12, d=96, P=3)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 8, 3, 12, 5, 3, 4, 3)
+    p = idx.export()
+    ks = np.random.default_rng(rerank_k).choice([1, 10, 25], size=len(Q)).astype(np.int32)
+    for T, L in ((300, 64), (900, 5)):
+        gi, gd = gpu_search(idx, Q, 25, T, L, ks=ks, precision=1, rerank_k=rerank_k)
+        oi, od = oracle.search(X, p["codebooks"], p["graph"], p["bridge_off"], p["bridge_ids"], Q, ks, T, L,
+                               precision=1, rerank_k=rerank_k)
+        np.testing.assert_array_equal(gi, oi)
+        fin = oi >= 0
+        np.testing.assert_allclose(gd[fin], od[fin], rtol=1e-4)
+        assert np.isinf(gd[~fin]).all()
+
+
+# ---------------------------------------------------------------- fp32 build against the oracle
+
+def test_f32_build_against_the_oracle():
+    """fp32 index build on a small GIST-shaped set.
+    Codebooks: the GPU sums members in int64 fixed point (order-free, far
+    finer than an fp32 ulp here) and divides in fp32; the oracle sums and
+    divides in fp64.  A centroid element then differs by a few fp32 ulps
+    (rtol 1e-5, atol 1e-6 on values of order 0.05), provided no assignment
+    flips on a near tie.  A fp32 distance over ds dims is within ds * 2^-24
+    relative of the exact one (ds products and ds sums, each rounded once);
+    the test checks that the nearest and second-nearest centroid of every
+    point differ by more than twice that for both distances, 4 ds 2^-24,
+    in every iteration.
+    Tables: fp32 subspace sums against fp64 within 1e-5 relative, and the
+    same codeword at every rank separated from its neighbours by more.
+    Bridge lists (built from the oracle's codebooks): equal to the oracle's
+    lists, except that a list may differ where fp32 rounding reorders
+    distances that agree to 1e-5 (each such list is checked against fp64
+    distances with that tolerance, and at most 1% of lists may differ)."""
+    from tests import literal
+    w = synth.scaled(synth.WORKLOADS["gist_like_1m_f32"], 3000, nq=40, K=10, d=96, P=3)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    P, K, ds, iters, seed, t, b = 3, 10, 32, 6, 11, 3, 4
+    idx = _index_cls().build(X, 6, P, K, iters, seed, t, b)
+    p = idx.export()
+    cb = oracle.kmeans(X, P, K, iters, seed)
+    for it in range(iters):
+        prev = oracle.kmeans(X, P, K, it, seed)      # the centroids iteration `it` assigns against
+        for s in range(P):
+            sub = X[:, s * ds:(s + 1) * ds].astype(np.float64)
+            D = ((sub[:, None, :] - prev[s][None].astype(np.float64)) ** 2).sum(-1)
+            D.sort(axis=1)
+            assert ((D[:, 1] - D[:, 0]) / D[:, 1]).min() > 4 * ds * 2.0 ** -24, "a near tie would make the comparison moot"
+    np.testing.assert_allclose(p["codebooks"], cb, rtol=1e-5, atol=1e-6)
+    # tables of the GPU build, sorted, against the oracle's on the same codebooks
+    sv, perm = idx.tables_device(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    sv, perm = sv.cpu().numpy().astype(np.float64), perm.cpu().numpy()
+    for i in range(len(Q)):
+        op, osv = oracle.sort_tables(oracle.tables(Q[i], p["codebooks"]))
+        np.testing.assert_allclose(sv[i], osv, rtol=1e-5)
+        for s in range(P):
+            gap = np.diff(osv[s]) > 1e-5 * osv[s][1:]
+            alone = np.concatenate([[gap[0]], gap[:-1] & gap[1:], [gap[-1]]])
+            assert (perm[i, s] == op[s])[alone].all()
+    # bridge graph from the oracle's codebooks
+    gb = _index_cls().build(X, 6, P, K, iters, seed, t, b, codebooks=cb).export()
+    off, ids, _ = oracle.bridge_graph(X, cb, t, b)
+    ys = literal.all_bridges(cb).astype(np.float64)
+    Xd = X.astype(np.float64)
+    D = (Xd ** 2).sum(1)[:, None] + (ys ** 2).sum(1)[None] - 2 * Xd @ ys.T     # fp64, every vector to every bridge
+    kth = np.sort(D, axis=1)[:, t - 1]                                          # each vector's t-th bridge distance
+    goff = gb["bridge_off"].astype(np.int64)
+    gids = gb["bridge_ids"].astype(np.int64)
+    nb = K ** P
+    differ = 0
+    for lid in range(nb):
+        g = gids[goff[lid]:goff[lid + 1]]
+        o = ids[off[lid]:off[lid + 1]].astype(np.int64)
+        if np.array_equal(g, o):
+            continue
+        differ += 1
+        tol = 1e-5 * max(D[o, lid].max() if len(o) else 0.0, D[g, lid].max() if len(g) else 0.0)
+        assert len(g) <= b and (D[g, lid] <= kth[g] * (1 + 1e-5)).all()      # chosen by each listed vector
+        assert (np.diff(D[g, lid]) >= -tol).all()                             # ascending up to rounding
+        assert len(g) == len(o) and abs(D[g, lid].sum() - D[o, lid].sum()) <= len(g) * tol
+    assert differ <= nb // 100, f"{differ} of {nb} bridge lists differ"
+
+
+# ---------------------------------------------------------------- budgets above 4096 (the serving stream's range)
+
+def test_large_budgets_uneven_k_bit_exact():
+    """Per-query budgets in (4096, 8192] with k in {1, 10, 100} on a bridge-heavy
+    index (R = 2, four lists of 32 codewords: most of the budget goes to
+    bridges, hundreds of thousands are extracted per query and the
+    multi-sequence state moves to global slots), against the oracle."""
+    w = synth.scaled(synth.WORKLOADS["hog_like_10m_u8"], 20000, nq=24, d=64, components=64)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 2, 4, 32, 3, 5, 8, 4)      # 1M bridge vectors, about 2% of them linked
+    parts = idx.export()
+    rng = np.random.default_rng(8192)
+    ks = rng.choice([1, 10, 100], size=len(Q)).astype(np.int32)
+    Ts = rng.integers(4097, 8193, size=len(Q)).astype(np.int32)
+    Ts[0] = 8192
+    gi, gd, st = gpu_search(idx, Q, 100, 8192, 64, ks=ks, Ts=Ts, stats=True)
+    print(f"[large-budget] evals {st[:, 0].mean():.0f}, bridges extracted {st[:, 4].mean():.0f}, "
+          f"moved {int(st[:, 10].sum())}, re-run {int(st[:, 9].sum())}", flush=True)
+    assert (st[:, 6] == 0).all()
+    assert (st[:, 10] == 1).any()          # global slots in use
+    assert (st[:, 0] == Ts).all()          # every budget spent
+    assert_search_equal(idx, parts, X, Q, 100, 8192, 64, ks=ks, Ts=Ts)
+
+
+def test_budget_beyond_lds_is_rejected():
+    """A visited set for 2^20 evaluations cannot live in one workgroup's LDS:
+    the search says so instead of running."""
+    from paper_1312_3062_amd import _abi
+    w = synth.scaled(synth.WORKLOADS["tiny_10k_u8"], 1000, nq=2)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 4, 2, 4, 2, 1, 1, 0)
+    with pytest.raises(_abi.AnnError) as e:
+        idx.search_device(torch.from_numpy(Q).cuda(), 10, 1 << 20)
+    assert e.value.status == _abi.ANN_EUNSUPPORTED and "LDS" in str(e.value)
+
+
+# ---------------------------------------------------------------- neighborhood-graph search without bridges
+
+@pytest.mark.parametrize("nseeds,T,L", [(1, 256, 64), (16, 500, 64), (70, 300, 8), (3, 0, 64), (0, 50, 64)])
+def test_graph_search_without_bridges_bit_exact(tiny, nseeds, T, L):
+    X, Q, p = tiny["X"], tiny["Q"], tiny["parts"]
+    seeds = (np.arange(nseeds, dtype=np.int64) * 7919 % len(X)).astype(np.int32)
+    if nseeds > 2:
+        seeds[-1] = seeds[0]                # a repeated seed is measured once
+    qd = torch.from_numpy(Q).cuda()
+    tr = torch.empty((len(Q), max(T, 1)), dtype=torch.int32, device="cuda")
+    ids, dd = tiny["idx"].search_graph_device(qd, 10, T, torch.from_numpy(seeds).cuda(), queue_len=L, trace=tr)
+    torch.cuda.synchronize()
+    oi, od, ot = oracle.search(X, p["codebooks"], p["graph"], p["bridge_off"], p["bridge_ids"], Q, 10, T, L,
+                               trace_len=max(T, 1), seeds=seeds.astype(np.uint32))
+    np.testing.assert_array_equal(ids.cpu().numpy(), oi)
+    np.testing.assert_array_equal(dd.cpu().numpy().astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
+    if T > 0:
+        np.testing.assert_array_equal(tr.cpu().numpy(), ot)
