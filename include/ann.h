@@ -289,6 +289,24 @@ int ann_search_graph_device(const ann_index* idx, const void* d_queries, int64_t
                             int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
 
 /*
+ * ann_search_device that allocates nothing, for callers that cannot call
+ * hipMalloc: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Its workspace is a buffer of
+ * ANN_NOALLOC_SCRATCH_BYTES compiled into the library: one copy on each GPU
+ * the library runs on, held until the process ends.  Same arguments, results
+ * and asynchrony as ann_search_device.
+ * Errors: as ann_search_device; ANN_EINVAL when the request's smallest
+ * workspace (per-query lists of about 8 bytes a query plus one
+ * multi-sequence slot) exceeds the buffer: search fewer queries per call.
+ * Every call on a GPU uses that GPU's one buffer: calls that overlap in time
+ * on one GPU (other streams, other threads) race and must not be made.
+ */
+#define ANN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ann_search_device_noalloc(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
+                              const int32_t* d_k, const int32_t* d_budget, const ann_search_params* params,
+                              int32_t* d_ids, void* d_dists, int32_t* d_stats, int32_t* d_trace, void* stream);
+
+/*
  * Launch autotuner: times the launch-tuning choices of ann_search_params
  * (lookahead, persistent, waves_per_cu, order) on the given device batch
  * and writes the fastest into *params; the other fields are kept.  Every

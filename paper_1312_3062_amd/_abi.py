@@ -63,6 +63,8 @@ SIGNATURES = {
                                     _vp, _vp, _i64, _vp]),
     "ann_search_graph_device": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _i32, C.POINTER(SearchParams), _vp, _vp,
                                        _vp, _vp, _vp]),
+    "ann_search_device_noalloc": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp, _vp,
+                                         _vp, _vp, _vp]),
     "ann_autotune": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp]),
     "ann_query_tables_device": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "ann_knn_device": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
