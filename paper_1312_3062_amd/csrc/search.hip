@@ -328,14 +328,19 @@ __device__ inline uint32_t home_bucket(uint32_t id, uint32_t nbk) {
     return uint32_t((uint64_t(id * 0x9E3779B1u) * nbk) >> 32);
 }
 
-// Lookups read two consecutive buckets at once (one LDS round trip); the
-// second counts only when the first is full, so the probe order is that of
-// bucket-by-bucket linear probing.
-__device__ inline int bucket_slot(uint4 v, uint32_t id) {
-    return v.x == id ? 0 : v.y == id ? 1 : v.z == id ? 2 : v.w == id ? 3 : -1;
+// A bucket's slots fill in order: a slot is claimed only as the bucket's
+// first empty one, and slots are emptied only all at once (a clear of the
+// whole table).  So a bucket with room has an empty last slot, and its
+// first empty slot is the number of ids it holds.
+__device__ inline bool bucket_open(uint4 v) { return v.w == ID_EMPTY; }
+__device__ inline bool bucket_has(uint4 v, uint32_t id) {
+    return min(min(v.x ^ id, v.y ^ id), min(v.z ^ id, v.w ^ id)) == 0u;
 }
-__device__ inline int bucket_free(uint4 v) {
-    return v.x == ID_EMPTY ? 0 : v.y == ID_EMPTY ? 1 : v.z == ID_EMPTY ? 2 : v.w == ID_EMPTY ? 3 : -1;
+__device__ inline uint32_t bucket_fill(uint4 v) {
+    return min(v.x + 1u, 1u) + min(v.y + 1u, 1u) + min(v.z + 1u, 1u) + min(v.w + 1u, 1u);
+}
+__device__ inline uint32_t bucket_index(uint4 v, uint32_t id) {  // v holds id
+    return v.x == id ? 0u : v.y == id ? 1u : v.z == id ? 2u : 3u;
 }
 
 // Slot of id, inserting it if absent.  fresh = it was absent.  Returns -1
@@ -345,16 +350,15 @@ __device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& f
     uint32_t b = home_bucket(id, nbk);
     for (uint32_t step = 0; step < 5 * nbk + 4; ++step) {
         const uint4 v = reinterpret_cast<const uint4*>(T)[b];
-        const int e = bucket_slot(v, id);
-        if (e >= 0) {
+        if (bucket_has(v, id)) {
             fresh = false;
-            return int(b * 4 + e);
+            return int(b * 4 + bucket_index(v, id));
         }
-        const int f = bucket_free(v);
-        if (f < 0) {
+        if (!bucket_open(v)) {
             b = (b + 1 == nbk) ? 0 : b + 1;
             continue;
         }
+        const uint32_t f = bucket_fill(v);
         const uint32_t old = atomicCAS(&T[b * 4 + f], ID_EMPTY, id);
         if (old == ID_EMPTY || old == id) {
             fresh = old == ID_EMPTY;
@@ -371,22 +375,38 @@ __device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& f
 constexpr uint32_t VISITED_FLAG = 0x80000000u;
 constexpr uint32_t DIST_BITS = 0x7FFFFFFFu;
 
-// Slot of id, or -1.
+// Lookups read two consecutive buckets at once (one LDS round trip); the
+// second counts only when the first is full, so the probe order is that of
+// bucket-by-bucket linear probing.  Slot of id, or -1.
 __device__ inline int set_find(const uint32_t* T, uint32_t nbk, uint32_t id) {
     uint32_t b = home_bucket(id, nbk);
     for (uint32_t step = 0; step < nbk; step += 2) {
         const uint32_t b2 = (b + 1 == nbk) ? 0 : b + 1;
         const uint4 v = reinterpret_cast<const uint4*>(T)[b];
         const uint4 w = reinterpret_cast<const uint4*>(T)[b2];
-        const int e = bucket_slot(v, id), e2 = bucket_slot(w, id);
-        const bool open = bucket_free(v) >= 0;
-        if (e >= 0) return int(b * 4 + e);
-        if (open) return -1;
-        if (e2 >= 0) return int(b2 * 4 + e2);
-        if (bucket_free(w) >= 0) return -1;
+        if (bucket_has(v, id)) return int(b * 4 + bucket_index(v, id));
+        if (bucket_open(v)) return -1;
+        if (bucket_has(w, id)) return int(b2 * 4 + bucket_index(w, id));
+        if (bucket_open(w)) return -1;
         b = (b2 + 1 == nbk) ? 0 : b2 + 1;
     }
     return -1;
+}
+
+// Whether the set holds id (the same probes, no slot).
+__device__ inline bool set_has(const uint32_t* T, uint32_t nbk, uint32_t id) {
+    uint32_t b = home_bucket(id, nbk);
+    for (uint32_t step = 0; step < nbk; step += 2) {
+        const uint32_t b2 = (b + 1 == nbk) ? 0 : b + 1;
+        const uint4 v = reinterpret_cast<const uint4*>(T)[b];
+        const uint4 w = reinterpret_cast<const uint4*>(T)[b2];
+        if (bucket_has(v, id)) return true;
+        if (bucket_open(v)) return false;
+        if (bucket_has(w, id)) return true;
+        if (bucket_open(w)) return false;
+        b = (b2 + 1 == nbk) ? 0 : b2 + 1;
+    }
+    return false;
 }
 
 // ------------------------------------------------------------------
@@ -921,7 +941,7 @@ k_search(SearchArgs a) {
                         if (with_dist) {
                             bool need = false;
                             uint32_t d = 0;
-                            if (pid != ID_EMPTY && set_find(H, a.hash_buckets, pid) < 0) {
+                            if (pid != ID_EMPTY && !set_has(H, a.hash_buckets, pid)) {
                                 const int ds = set_find(DK, a.dc_buckets, pid);
                                 if (ds >= 0)
                                     d = DV[ds] & DIST_BITS;
@@ -1023,7 +1043,7 @@ k_search(SearchArgs a) {
                     ac_id = nid;
                     bool need = false, known = false;
                     int slot = 0;
-                    if (ac_id != ID_EMPTY && set_find(H, a.hash_buckets, ac_id) < 0) {
+                    if (ac_id != ID_EMPTY && !set_has(H, a.hash_buckets, ac_id)) {
                         known = true;
                         slot = set_insert(DK, a.dc_buckets, ac_id, need);
                         if (slot < 0) {
