@@ -92,7 +92,7 @@ def precision_leg(idx, w, X, Q, gt, T, torch, steps=10):
     return res
 
 
-def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
+def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None, requests=None):
     """Poisson request streams at fractions of the plain saturation rate, served
     (continuous batching) and plain (one launch per request).  With fixed_k /
     fixed_budget every request uses them (the recall >= 0.9 operating point);
@@ -111,22 +111,24 @@ def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
 
     pool = synth.queries(w, nq=args.serve_pool)
     srv = Server(idx, w.d, "u8" if w.dtype == "u8" else "f32", slots=4, slot_queries=4096, kmax=100,
-                 queue_len=w.queue_len)
-    probe = stream(1.0, 99)[:120]
+                 max_budget=max(8192, fixed_budget or 0), queue_len=w.queue_len)
+    probe = stream(1.0, 99)[:200]
     srv.run_served(probe[:20], pool)  # warm-up of both paths
     srv.run_plain(probe[:20], pool)
     svc = srv.plain_service_time(probe, pool)
     sat = 1.0 / svc
     log(f"[serve] plain service time {svc * 1e3:.2f} ms/request -> saturation {sat:.1f} requests/s")
     runs, checks = [], {}
-    for i, f in enumerate((0.5, 0.8, 1.1)):
-        reqs = stream(f * sat, i)[:args.serve_requests]
-        keep = f == 0.8
+    for i, f in enumerate(args.serve_loads):
+        reqs = stream(f * sat, i)[:requests or args.serve_requests]
+        keep = i == 1
         a = srv.run_served(reqs, pool, f * sat, keep_ids=keep)
         b = srv.run_plain(reqs, pool, f * sat, keep_ids=keep)
+        offered = sum(r.batch for r in reqs) / max(1e-9, reqs[-1].arrival_s - reqs[0].arrival_s)
         for r in (a, b):
             sm = r.summary()
             sm["load"] = f
+            sm["offered_qps"] = round(offered, 1)
             runs.append(sm)
             log(f"[serve] load {f:.1f}x {sm['mode']:6s}: {sm['qps']:.0f} QPS, p50 {sm['p50_ms']:.2f} ms, "
                 f"p99 {sm['p99_ms']:.2f} ms, {sm['launches']} launches")
@@ -139,9 +141,16 @@ def serving_leg(idx, w, args, gt_fn, fixed_k=None, fixed_budget=None):
             checks["recall@10_k>=10"] = round(recall_at(a.ids[sel], gt, 10), 4)
             log(f"[serve] same ids served and plain: {checks['mix_invariant']}; "
                 f"recall@10 over {len(sel)} queries with k>=10: {checks['recall@10_k>=10']}")
+    served = [r for r in runs if r["mode"] == "served"]
+    plain = [r for r in runs if r["mode"] == "plain"]
+    keeps = lambda r: r["qps"] >= 0.95 * r["offered_qps"]  # noqa: E731  (kept up with the arrivals)
+    srv.close()
     return {"index": w.name, "k": fixed_k or "1|10|100", "budget": fixed_budget or "128..8192",
-            "requests_per_run": args.serve_requests, "plain_service_ms": round(svc * 1e3, 3),
-            "plain_saturation_rps": round(sat, 2), "runs": runs, **checks}
+            "requests_per_run": len(reqs), "plain_service_ms": round(svc * 1e3, 3),
+            "plain_saturation_rps": round(sat, 2), "runs": runs,
+            "served_max_qps": max(r["qps"] for r in served), "plain_max_qps": max(r["qps"] for r in plain),
+            "served_keeps_up_to_load": max([r["load"] for r in served if keeps(r)], default=None),
+            "plain_keeps_up_to_load": max([r["load"] for r in plain if keeps(r)], default=None), **checks}
 
 
 def bridge_alpha(idx):
@@ -156,10 +165,12 @@ def bridge_alpha(idx):
     return {"alpha": linked / nb, "linked": int(linked), "nonempty_share": float(np.count_nonzero(np.diff(off))) / nb}
 
 
-def bench_uneven(w, args, torch):
+def uneven_leg(w, args, torch, serve_mixed=False, cpu_baseline=True):
     """The 10M workload: 100K queries with their own k (1, 10, 100) and budget
     (log-uniform 64..4096) searched by one persistent launch captured in a HIP
-    graph and replayed; recall@10 over the queries with k >= 10."""
+    graph and replayed; recall@10 over the queries with k >= 10.  With
+    serve_mixed, request streams with k in {1, 10, 100} and budgets 128..8192
+    on the same index, served and plain.  Returns the figures as a dict."""
     from paper_1312_3062_amd import Index, knn_device, recall_at, synth
     t0 = time.time()
     X = synth.base_vectors(w)
@@ -227,9 +238,10 @@ def bench_uneven(w, args, torch):
     achieved = float(B.sum()) / (kms * 1e-3) / 1e9
     log(f"[bench] graph replay: {kms:.3f} ms per batch, {qps:.0f} QPS, same ids as eager: {same}; "
         f"algorithmic {B.sum() / 1e9:.3f} GB -> {achieved:.1f} GB/s")
+    del g, ws, out
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if cpu_baseline and not args.no_cpu_baseline:
         import oracle
         parts = idx.export()
         m = args.cpu_sample or 4000
@@ -240,24 +252,23 @@ def bench_uneven(w, args, torch):
         eq = bool(all(np.array_equal(oi[i, :ks[i]], ids[i, :ks[i]]) for i in range(m)))
         cpu = {"value": round(m / cpu_s, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
                "sample": f"first {m} of {nq} queries with their own k and budget ({cpu_s:.1f} s), single-threaded "
-                         f"C oracle on the GPU-built index; ids identical to the GPU: {eq}"}
+                         f"C oracle on the GPU-built index; ids identical to the GPU: {eq}", "host": host_info()}
         log(f"[bench] oracle: {m} queries in {cpu_s:.1f}s -> {m / cpu_s:.1f} QPS (ids equal: {eq})")
 
     serving = None
-    if args.serve_mixed:
+    if serve_mixed:
         def gt_fn(qs):
             r, _ = knn_device(xd, torch.from_numpy(np.ascontiguousarray(qs)).cuda(), 10)
             torch.cuda.synchronize()
             return r.cpu().numpy()
 
-        serving = {"mixed_k_budget": serving_leg(idx, w, args, gt_fn)}
+        serving = serving_leg(idx, w, args, gt_fn, requests=args.serve_requests_10m)
     del xd
-    line = {
-        "metric": f"QPS of one uneven batch (k in 1|10|100, budget log-uniform 64..4096), "
-                  f"{w.n // 1_000_000}M x{w.d} uint8",
-        "value": round(qps, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall * 1000.0 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+    from paper_1312_3062_amd.profiling import read_traffic_record
+    trec = read_traffic_record(os.path.join(ROOT, "profiles", f"k_search_{w.name}_traffic.md"))
+    traffic = trec["bytes_per_launch"] if trec and trec.get("workload") == f"{w.name} uneven nq={nq}" else None
+    return {
+        "value": round(qps, 1), "ms_per_step": round(wall * 1000.0 / args.steps, 4),
         "config": {"workload": w.name, "n": w.n, "d": w.d, "queries": nq, "k": "1|10|100",
                    "budget": "log-uniform 64..4096", "mean_budget": round(float(Ts.mean()), 1),
                    "queue_len": w.queue_len, "graph_k": w.graph_k, "P": w.P, "K": w.K, "bridge_t": w.bridge_t,
@@ -265,12 +276,134 @@ def bench_uneven(w, args, torch):
                    "hip_graph": True, "graph_ids_equal_eager": same, "build_s": round(build_s, 2),
                    "bridge_alpha": round(alpha["alpha"], 5), "bridges_nonempty": round(alpha["nonempty_share"], 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": "k_search",
-                     "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": int(B.sum())},
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "kernel": "k_search", "kernel_ms": round(kms, 4), "algorithmic_bytes_per_launch": int(B.sum())},
         "cpu_baseline": cpu,
         "serving": serving,
     }
+
+
+def bench_uneven(w, args, torch):
+    """One JSON line for the 10M workload alone (--workload hog_like_10m_u8)."""
+    leg = uneven_leg(w, args, torch, serve_mixed=args.serve_mixed)
+    line = {
+        "metric": f"QPS of one uneven batch (k in 1|10|100, budget log-uniform 64..4096), "
+                  f"{w.n // 1_000_000}M x{w.d} uint8",
+        "value": leg["value"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": leg["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic", "config": leg["config"],
+        "roofline": leg["roofline"], "cpu_baseline": leg["cpu_baseline"],
+        "serving": {"mixed_k_budget": leg["serving"]} if leg["serving"] else None,
+    }
     print(json.dumps(line), flush=True)
+
+
+def host_info() -> dict:
+    """The host the oracle is timed on: logical CPUs, the ones this process may
+    use, the CPU model and whether SMT is on."""
+    info = {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)), "cpu_model": None, "smt": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        with open("/sys/devices/system/cpu/smt/active") as f:
+            info["smt"] = f.read().strip() == "1"
+    except OSError:
+        pass
+    return info
+
+
+def graph_search_leg(idx, w, Q, gt, torch, bridged, seeds_count=16):
+    """The neighborhood-graph search without bridges (Sec. 2.2, the iterative
+    search Sec. 5.3 compares against): fixed seeds, best first over the kNN
+    graph, on the same budgets as the bridged search, doubling until it too
+    reaches recall@10 >= 0.9 (or 16384)."""
+    from paper_1312_3062_amd import recall_at, synth
+    qd = torch.from_numpy(Q).cuda()
+    seeds = torch.from_numpy(synth.graph_seeds(w, seeds_count)).cuda()
+    out = (torch.empty((len(Q), w.k), dtype=torch.int32, device="cuda"),
+           torch.empty((len(Q), w.k), dtype=torch.int32, device="cuda"))
+
+    def kernel_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    rows, pending = [], sorted(set(b["budget"] for b in bridged))
+    from paper_1312_3062_amd._abi import AnnError
+    while pending:
+        T = pending.pop(0)
+        try:
+            g_ms = kernel_ms(lambda: idx.search_graph_device(qd, w.k, T, seeds, queue_len=w.queue_len, out=out))
+        except AnnError as e:  # a budget whose visited set does not fit one workgroup's LDS
+            log(f"[graph] T={T}: {e}")
+            break
+        g_rec = recall_at(out[0].cpu().numpy(), gt, w.k)
+        b_ms = kernel_ms(lambda: idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out))
+        b_rec = recall_at(out[0].cpu().numpy(), gt, w.k)
+        rows.append({"budget": T, "graph_recall@10": round(g_rec, 4), "graph_kernel_ms": round(g_ms, 3),
+                     "bridged_recall@10": round(b_rec, 4), "bridged_kernel_ms": round(b_ms, 3)})
+        log(f"[graph] T={T}: no bridges recall@10 {g_rec:.4f} ({g_ms:.3f} ms), bridged {b_rec:.4f} ({b_ms:.3f} ms)")
+        if not pending and g_rec < 0.9 and T < 16384:
+            pending.append(2 * T)
+    first = lambda key: next((r for r in rows if r[key] >= 0.9), None)  # noqa: E731
+    g9, b9 = first("graph_recall@10"), first("bridged_recall@10")
+    res = {"seeds": seeds_count, "sweep": rows}
+    if g9 and b9:
+        res["qps_at_recall_0.9"] = {"graph": round(len(Q) / (g9["graph_kernel_ms"] * 1e-3), 1),
+                                    "bridged": round(len(Q) / (b9["bridged_kernel_ms"] * 1e-3), 1),
+                                    "graph_budget": g9["budget"], "bridged_budget": b9["budget"]}
+    return res
+
+
+def scan_overhead_leg(idx, w, X, Q, torch, visited=10_000):
+    """Fig. 5 of the paper: the time to visit `visited` reference vectors by the
+    search (budget = visited) against a linear scan computing the distances to
+    `visited` reference vectors (the first rows of X, on matrix cores), for the
+    same queries; the overhead is the difference."""
+    from paper_1312_3062_amd import knn_device
+    qd = torch.from_numpy(Q).cuda()
+    xs = torch.from_numpy(np.ascontiguousarray(X[:visited])).cuda()
+    st = torch.empty((len(Q), 12), dtype=torch.int32, device="cuda")
+    idx.search_device(qd, w.k, visited, queue_len=w.queue_len, stats=st)
+    torch.cuda.synchronize()
+    stn = st.cpu().numpy().astype(np.float64)
+    evals = float(stn[:, 0].mean())
+
+    def kernel_ms(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record()
+            fn()
+            b.record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    s_ms = kernel_ms(lambda: idx.search_device(qd, w.k, visited, queue_len=w.queue_len))
+    l_ms = kernel_ms(lambda: knn_device(xs, qd, w.k))
+    per_q = lambda ms: ms * 1e3 / len(Q)  # noqa: E731  (microseconds per query)
+    log(f"[scan] visiting {visited} vectors: search {s_ms:.3f} ms, linear scan {l_ms:.3f} ms "
+        f"for {len(Q)} queries (evaluations per query {evals:.0f})")
+    return {"visited": visited, "queries": len(Q), "evals_per_query": round(evals, 1),
+            "ref_pops_per_query": round(float(stn[:, 1].mean()), 1), "rows_per_query": round(float(stn[:, 7].mean()), 1),
+            "bridge_pops_per_query": round(float(stn[:, 2].mean()), 1),
+            "search_ms": round(s_ms, 3), "linear_scan_ms": round(l_ms, 3),
+            "search_us_per_query": round(per_q(s_ms), 3), "linear_scan_us_per_query": round(per_q(l_ms), 3),
+            "overhead_us_per_query": round(per_q(s_ms - l_ms), 3), "ratio": round(s_ms / max(l_ms, 1e-9), 2)}
 
 
 def oracle_all_cores(oracle, X, parts, Q, sample, passes, w, T, gpu_ids):
@@ -278,7 +411,7 @@ def oracle_all_cores(oracle, X, parts, Q, sample, passes, w, T, gpu_ids):
     slice of the queries (the C oracle runs outside the interpreter lock),
     `passes` passes as in the single-threaded timing."""
     from concurrent.futures import ThreadPoolExecutor
-    cores = max(1, min(16, os.cpu_count() or 1))
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
     bounds = np.linspace(0, sample, cores + 1).astype(int)
 
     def part(i):
@@ -297,6 +430,7 @@ def oracle_all_cores(oracle, X, parts, Q, sample, passes, w, T, gpu_ids):
                 same = same and bool(np.array_equal(oi, gpu_ids[lo:lo + len(oi)]))
     secs = time.perf_counter() - t0
     return {"value": round(sample * passes / secs, 2), "unit": "queries/s", "cores": cores,
+            "cap": "at most 16 threads: the host's CPU share for one GPU",
             "sample": f"the same {sample} queries x {passes} passes split over {cores} threads ({secs:.1f} s); "
                       f"ids identical to the GPU: {same}"}
 
@@ -313,12 +447,20 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="queries for the oracle baseline (0: auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-vs-plain request streams")
-    ap.add_argument("--serve-requests", type=int, default=400, help="requests per served / plain run")
+    ap.add_argument("--serve-requests", type=int, default=5000, help="requests per served / plain run")
+    ap.add_argument("--serve-requests-10m", type=int, default=2000,
+                    help="requests per served / plain run of the mixed stream on the 10M index")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 1.1, 2.0, 4.0],
+                    help="request rates as multiples of the plain saturation rate")
     ap.add_argument("--serve-mixed", action="store_true",
                     help="also serve a stream with k in {1,10,100} and budgets 128..8192 per request")
-    ap.add_argument("--serve-pool", type=int, default=200_000, help="query vectors the request streams draw")
+    ap.add_argument("--serve-pool", type=int, default=800_000, help="query vectors the request streams draw")
     ap.add_argument("--bridge-t", type=int, default=-1, help="override the workload's bridges per vector (t)")
     ap.add_argument("--bridge-b", type=int, default=-1, help="override the workload's vectors per bridge (b; 0 = all)")
+    ap.add_argument("--no-scale", action="store_true",
+                    help="skip the 10M x 128 legs (uneven batch, mixed request stream)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the graph search without bridges and the linear-scan overhead legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a copy-like kernel over 1 GiB (calibrates hardware traffic counters)")
     args = ap.parse_args()
@@ -486,6 +628,11 @@ def main():
             serving["mixed_k_budget"] = serving_leg(idx, w, args, gt_fn)
         del xd2
 
+    graph_leg = scan_leg = None
+    if not args.no_extra and X.dtype == np.uint8:
+        graph_leg = [graph_search_leg(idx, w, Q, gt, torch, sweep, seeds_count=c) for c in (16, 256)]
+        scan_leg = scan_overhead_leg(idx, w, X, Q, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -504,7 +651,8 @@ def main():
         done = sample * passes
         cpu = {"value": round(done / cpu_s, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
                "sample": f"first {sample} of {nq} queries x {passes} passes at T={T} ({cpu_s:.1f} s), "
-                         f"single-threaded C oracle on the GPU-built index; ids identical to the GPU: {same}"}
+                         f"single-threaded C oracle on the GPU-built index; ids identical to the GPU: {same}",
+               "host": host_info()}
         log(f"[bench] oracle: {done} queries in {cpu_s:.1f}s -> {done / cpu_s:.1f} QPS (ids equal: {same})")
         cpu["all_cores"] = oracle_all_cores(oracle, X, parts, Q, sample, passes, w, T, out[0][:sample].cpu().numpy())
         log(f"[bench] oracle on {cpu['all_cores']['cores']} threads: {cpu['all_cores']['value']} QPS")
@@ -541,7 +689,20 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "precision": precision,
+        "graph_search_without_bridges": graph_leg,
+        "overhead_vs_linear_scan": scan_leg,
     }
+    if not args.no_scale and X.dtype == np.uint8 and not overridden:
+        # the 10M x 128 workload: its uneven batch (a second roofline figure,
+        # the HBM-resident case) and the mixed request stream served over it
+        del idx, qd, out, stats
+        torch.cuda.empty_cache()
+        try:
+            line["scale_10m"] = uneven_leg(synth.WORKLOADS["hog_like_10m_u8"], args, torch,
+                                           serve_mixed=not args.no_serve, cpu_baseline=False)
+        except Exception as e:  # reported in the line; the headline above stands
+            log(f"[bench] 10M leg failed: {e!r}")
+            line["scale_10m"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
 
 

@@ -319,6 +319,95 @@ int ann_search_device_noalloc(const ann_index* idx, const void* d_queries, int64
 int ann_autotune(const ann_index* idx, const void* d_queries, int64_t nq, int32_t k, int32_t budget,
                  const int32_t* d_k, const int32_t* d_budget, ann_search_params* params, void* stream);
 
+/* ------------------------------------------------------------------ */
+/* Serving: continuous batching over a device-resident index           */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A request server: requests (a batch of query vectors with their own k and
+ * budget, each query searched by Alg. 1 as in ann_search) are queued by
+ * ann_server_submit and served by micro-batch launches on `slots` streams.
+ * Whenever a slot is free, pending requests are taken in arrival order into
+ * one micro-batch while its footprint fits:
+ *  - device memory: the micro-batch's query rows, k and budget per query,
+ *    result rows and search workspace are one chunk of a device arena of
+ *    `device_bytes`, beside the chunks of the micro-batches in flight;
+ *  - LDS: each query, while resident on a compute unit, occupies the LDS
+ *    layout of its budget class (ann_server_footprint); the queries in
+ *    flight hold at most `lds_rounds` times the chip's LDS.
+ * Requests arriving while others run are admitted as slots and memory free
+ * up; their launches overlap on the device.  Results are those of
+ * ann_search for each query: independent of the mix.
+ * A server is driven by one thread; it switches to the index's device
+ * inside each call and back.
+ */
+typedef struct ann_server ann_server;
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(ann_server_params) */
+    int32_t slots;            /* micro-batches in flight at once, 1..16 */
+    int32_t slot_queries;     /* most queries in one micro-batch (and in one request) */
+    int32_t kmax;             /* largest k of a request, 1..1024 */
+    int32_t max_budget;       /* largest budget of a request */
+    int32_t lds_rounds;       /* LDS in flight, in multiples of the chip's LDS (0: 2) */
+    int64_t device_bytes;     /* device arena (0: `slots` full micro-batches) */
+    ann_search_params search; /* queue length, precision, launch tuning */
+} ann_server_params;
+
+typedef struct {
+    int64_t pending;          /* requests waiting for admission */
+    int64_t busy_slots;       /* micro-batches in flight */
+    int64_t launches;         /* micro-batches launched so far */
+    int64_t lds_in_flight, lds_limit;          /* bytes */
+    int64_t device_in_flight, device_bytes;    /* bytes of the arena */
+} ann_server_info;
+
+/*
+ * Create a server over idx (which must outlive it).  Allocates the device
+ * arena and pinned host staging for each slot.
+ * Errors: ANN_EINVAL (bad parameters, an arena smaller than one full
+ * micro-batch, one query at max_budget needing more LDS than the chip),
+ * ANN_ENOMEM, ANN_EDEVICE.
+ */
+int ann_server_create(const ann_index* idx, const ann_server_params* params, ann_server** out);
+
+/* LDS (while resident) and device bytes of a request of nq queries. */
+int ann_server_footprint(const ann_server* server, int32_t nq, int32_t k, int32_t budget, int64_t* lds_bytes,
+                         int64_t* device_bytes);
+
+/*
+ * Queue a request: queries host, nq x d (index dtype), copied before the
+ * call returns.  *ticket identifies it.  Pending requests are admitted
+ * here and in ann_server_progress.
+ * Errors: ANN_EINVAL (nq outside 1..slot_queries, k above kmax, budget
+ * above max_budget, an LDS footprint the server can never admit),
+ * ANN_EDEVICE.
+ */
+int ann_server_submit(ann_server* server, const void* queries, int32_t nq, int32_t k, int32_t budget,
+                      int64_t* ticket);
+
+/*
+ * Retire finished micro-batches and admit pending requests; never blocks.
+ * Writes up to `cap` tickets of requests completed since the last call to
+ * done[] and their count to *n_done.
+ */
+int ann_server_progress(ann_server* server, int64_t* done, int32_t cap, int32_t* n_done);
+
+/*
+ * Results of a completed request: ids host nq x k int32, dists host nq x k
+ * (int32 for u8, float for f32), as ann_search writes them.  The ticket is
+ * released.  Errors: ANN_EINVAL (unknown ticket), ANN_ESTATE (not done).
+ */
+int ann_server_result(ann_server* server, int64_t ticket, int32_t* ids, void* dists);
+
+/* Block until every submitted request has completed. */
+int ann_server_drain(ann_server* server);
+
+int ann_server_get_info(const ann_server* server, ann_server_info* info);
+
+/* Wait for the micro-batches in flight, then free everything. */
+void ann_server_destroy(ann_server* server);
+
 /*
  * Query preprocessing alone (Sec. 4.2): for each query the P x K squared
  * distances to the codewords, each subspace sorted ascending by

@@ -37,6 +37,18 @@ class IndexInfo(C.Structure):
                 ("n_bridge_entries", C.c_int64), ("device_bytes", C.c_int64)]
 
 
+class ServerParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("slots", C.c_int32), ("slot_queries", C.c_int32), ("kmax", C.c_int32),
+                ("max_budget", C.c_int32), ("lds_rounds", C.c_int32), ("device_bytes", C.c_int64),
+                ("search", SearchParams)]
+
+
+class ServerInfo(C.Structure):
+    _fields_ = [("pending", C.c_int64), ("busy_slots", C.c_int64), ("launches", C.c_int64),
+                ("lds_in_flight", C.c_int64), ("lds_limit", C.c_int64), ("device_in_flight", C.c_int64),
+                ("device_bytes", C.c_int64)]
+
+
 class AnnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"[{status}] {msg}")
@@ -66,6 +78,14 @@ SIGNATURES = {
     "ann_search_device_noalloc": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp, _vp,
                                          _vp, _vp, _vp]),
     "ann_autotune": (_i32, [_vp, _vp, _i64, _i32, _i32, _vp, _vp, C.POINTER(SearchParams), _vp]),
+    "ann_server_create": (_i32, [_vp, C.POINTER(ServerParams), C.POINTER(_vp)]),
+    "ann_server_footprint": (_i32, [_vp, _i32, _i32, _i32, C.POINTER(_i64), C.POINTER(_i64)]),
+    "ann_server_submit": (_i32, [_vp, _vp, _i32, _i32, _i32, C.POINTER(_i64)]),
+    "ann_server_progress": (_i32, [_vp, _vp, _i32, C.POINTER(_i32)]),
+    "ann_server_result": (_i32, [_vp, _i64, _vp, _vp]),
+    "ann_server_drain": (_i32, [_vp]),
+    "ann_server_get_info": (_i32, [_vp, C.POINTER(ServerInfo)]),
+    "ann_server_destroy": (None, [_vp]),
     "ann_query_tables_device": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "ann_knn_device": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "ann_last_error": (_cp, []),

@@ -53,6 +53,9 @@ struct SearchLaunch {
 
 int launch_search(const SearchLaunch& a);
 int search_workspace_bytes(const SearchLaunch& a, int64_t* bytes, bool minimum = false);
+// LDS one query of this launch occupies on a compute unit (allocation
+// granules included), the largest over the launch's budget classes.
+int search_lds_per_query(const SearchLaunch& a, int64_t* bytes);
 int search_min_workspace(const ann_index* idx, int64_t nq, int32_t k, int32_t budget, const ann_search_params* sp,
                          int64_t* bytes);
 int launch_tables(const ann_index* idx, const void* d_q, int64_t nq, void* d_sorted, int32_t* d_perm,

@@ -1599,6 +1599,16 @@ int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes, bool minimum) 
     return ANN_OK;
 }
 
+int search_lds_per_query(const SearchLaunch& s, int64_t* bytes) {
+    ClassPlans cl;
+    int rc = make_class_plans(s, cl);
+    if (rc) return rc;
+    int64_t most = 0;
+    for (const auto& c : cl) most = std::max<int64_t>(most, ceil_div(c.pl.lds1, kLdsGranule) * kLdsGranule);
+    *bytes = most;
+    return ANN_OK;
+}
+
 int launch_search(const SearchLaunch& s) {
     if (s.nq == 0) return ANN_OK;
     ClassPlans cl;

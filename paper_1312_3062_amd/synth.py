@@ -165,3 +165,10 @@ def request_stream(w: Workload, total_queries: int, rate_rps: float, seed_offset
         out.append(Request(clock, used, b, int(rng.choice([1, 10, 100])), int(rng.choice(budgets))))
         used += b
     return out
+
+
+def graph_seeds(w: Workload, count: int = 16) -> np.ndarray:
+    """Fixed seed vectors of the neighborhood-graph search without bridges:
+    `count` distinct reference ids drawn once (the same for every query)."""
+    rng = np.random.default_rng(5000 + w.seed_base)
+    return rng.choice(w.n, size=min(count, w.n), replace=False).astype(np.int32)
