@@ -284,9 +284,23 @@ def uneven_leg(w, args, torch, serve_mixed=False, cpu_baseline=True):
     }
 
 
+def copy_probe(torch):
+    """bitwise_not over 2^28 int32: reads 1 GiB, writes 1 GiB, no reuse (the
+    known traffic that calibrates the hardware counters)."""
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.bitwise_not(src, out=dst)
+    torch.cuda.synchronize()
+    del src, dst
+    log("[bench] copy probe: 3 x bitwise_not over 1 GiB")
+
+
 def bench_uneven(w, args, torch):
     """One JSON line for the 10M workload alone (--workload hog_like_10m_u8)."""
     leg = uneven_leg(w, args, torch, serve_mixed=args.serve_mixed)
+    if args.copy_probe:
+        copy_probe(torch)
     line = {
         "metric": f"QPS of one uneven batch (k in 1|10|100, budget log-uniform 64..4096), "
                   f"{w.n // 1_000_000}M x{w.d} uint8",
@@ -593,14 +607,7 @@ def main():
         f"algorithmic {B.sum() / 1e9:.3f} GB/launch -> {achieved:.1f} GB/s")
 
     if args.copy_probe:
-        # bitwise_not over 2^28 int32: reads 1 GiB, writes 1 GiB, no reuse
-        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.bitwise_not(src, out=dst)
-        torch.cuda.synchronize()
-        del src, dst
-        log("[bench] copy probe: 3 x bitwise_not over 1 GiB")
+        copy_probe(torch)
 
     # HBM traffic of the search kernel, from the counter runs kept with the
     # profiles (only if taken on the current kernel sources and this workload)

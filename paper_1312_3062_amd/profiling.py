@@ -5,12 +5,16 @@
       durations of its last N dispatches
 
   python -m paper_1312_3062_amd.profiling traffic --fetch FETCH.csv --write WRITE.csv \\
-          --kernel REGEX --copy REGEX --copy-bytes B [--last N]
+          --kernel REGEX --copy REGEX --copy-bytes B [--last N] [--per-launch M]
       HBM traffic of a kernel from two counter-collection runs (FETCH_SIZE,
       then WRITE_SIZE, KiB per dispatch).  Each counter is divided by what it
       reads for a copy-like kernel that moves a known B bytes in and B bytes
       out, which removes the counters' own scale.  Prints a markdown summary
       and one machine-readable line (an HTML comment) that bench.py reads.
+
+  python -m paper_1312_3062_amd.profiling sq RUN_A.csv [RUN_B.csv] --kernel REGEX --last N --queries Q
+      SQ counters of a kernel (averaged over its last N dispatches), per
+      dispatch and per query, with the VALU / scalar / LDS busy shares.
 
 The machine-readable line carries a hash of the search kernel's code
 (comments aside): a figure taken on other code is not reported.
@@ -97,7 +101,38 @@ def counter_values(path: str, counter: str, kernel_re: str):
     return [by_dispatch[k] for k in sorted(by_dispatch)]
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel_re: str, copy_re: str, copy_bytes: int, last: int):
+def sq_table(csvs, kernel_re: str, last: int, queries: int) -> str:
+    """SQ counters of a kernel's last `last` dispatches (averaged), per dispatch
+    and per query.  Cycle counters of the SQ are in units of 4 cycles; the
+    busy shares divide by the SIMDs' time (GRBM_GUI_ACTIVE per XCD x 32 CUs x
+    4 SIMDs; the same for VALU and the scalar unit's issue slots)."""
+    vals = {}
+    for path in csvs:
+        by = collections.OrderedDict()
+        for r in _rows(path):
+            if re.search(kernel_re, r["Kernel_Name"]):
+                by.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        for d in list(by)[-last:]:
+            for k, v in by[d].items():
+                vals.setdefault(k, []).append(v)
+    avg = {k: sum(v) / len(v) for k, v in vals.items()}
+    lines = ["| counter | per dispatch | per query |", "|---|---|---|"]
+    for k in sorted(avg):
+        lines.append(f"| {k} | {avg[k]:.4g} | {avg[k] / max(queries, 1):.4g} |")
+    if "GRBM_GUI_ACTIVE" in avg:
+        simd_quads = avg["GRBM_GUI_ACTIVE"] * 32 * 4 / 4.0  # per XCD cycles x SIMDs, in 4-cycle units
+        for k in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS", "SQ_INSTS_VALU", "SQ_INSTS_SALU"):
+            if k in avg:
+                lines.append(f"| {k} / SIMD time | {avg[k] / simd_quads:.3f} | |")
+    if "SQ_WAVE_CYCLES" in avg:
+        for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY"):
+            if k in avg:
+                lines.append(f"| {k} / SQ_WAVE_CYCLES | {avg[k] / avg['SQ_WAVE_CYCLES']:.3f} | |")
+    return "\n".join(lines)
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel_re: str, copy_re: str, copy_bytes: int, last: int,
+            per_launch: int = 1):
     kib = copy_bytes / 1024.0
     cf = counter_values(fetch_csv, "FETCH_SIZE", copy_re)
     cw = counter_values(write_csv, "WRITE_SIZE", copy_re)
@@ -109,8 +144,9 @@ def traffic(fetch_csv: str, write_csv: str, kernel_re: str, copy_re: str, copy_b
     f_scale = (sum(cf) / len(cf)) / kib
     w_scale = (sum(cw) / len(cw)) / kib
     kf, kw = kf[-last:], kw[-last:]
-    fetch_b = sum(kf) / len(kf) / f_scale * 1024.0
-    write_b = sum(kw) / len(kw) / w_scale * 1024.0
+    # a launch may be several dispatches of the kernel (one per budget class)
+    fetch_b = sum(kf) / len(kf) * per_launch / f_scale * 1024.0
+    write_b = sum(kw) / len(kw) * per_launch / w_scale * 1024.0
     return {"fetch_bytes": fetch_b, "write_bytes": write_b, "bytes_per_launch": fetch_b + write_b,
             "fetch_scale": f_scale, "write_scale": w_scale, "copy_dispatches": [len(cf), len(cw)],
             "kernel_dispatches": [len(kf), len(kw)],
@@ -147,7 +183,16 @@ def main(argv=None):
     c.add_argument("--last", type=int, default=1 << 30)
     c.add_argument("--algorithmic-bytes", type=float, default=0.0)
     c.add_argument("--workload", default="")
+    c.add_argument("--per-launch", type=int, default=1, help="dispatches of the kernel per launch")
+    q = sub.add_parser("sq")
+    q.add_argument("csv", nargs="+")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--last", type=int, default=1)
+    q.add_argument("--queries", type=int, default=1)
     a = ap.parse_args(argv)
+    if a.cmd == "sq":
+        print(sq_table(a.csv, a.kernel, a.last, a.queries))
+        return
     if a.cmd == "trace":
         print(trace_table(a.csv))
         if a.kernel:
@@ -156,7 +201,7 @@ def main(argv=None):
                 print(f"\nLast {len(ds)} `{a.kernel}` dispatches (ms): " + ", ".join(f"{d:.3f}" for d in ds) +
                       f" (mean {sum(ds) / len(ds):.3f} ms)")
         return
-    r = traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes, a.last)
+    r = traffic(a.fetch, a.write, a.kernel, a.copy, a.copy_bytes, a.last, a.per_launch)
     print(f"| quantity | value |\n|---|---|")
     print(f"| copy kernel: FETCH_SIZE / bytes read | {r['fetch_scale']:.4f} |")
     print(f"| copy kernel: WRITE_SIZE / bytes written | {r['write_scale']:.4f} |")
