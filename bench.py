@@ -313,6 +313,87 @@ def bench_uneven(w, args, torch):
     print(json.dumps(line), flush=True)
 
 
+def bridge_sweep(w, args, torch):
+    """The bridge-graph rule and the codebooks (Sec. 4.1, Table 1, Sec. 5.2's
+    study of partitions and clusters) on the 1M x 128 data: for P in {2, 4}
+    subspaces, several K and the rules (t, b) in {(1, all), (1, 5), (100, 5)},
+    the reference vectors linked to bridge vectors (#reference), alpha =
+    #reference / K^P, and the search's recall@10 and queries/s at the
+    smallest budget on the doubling grid (refined by eighths) that reaches
+    recall@10 >= 0.9.  Every index shares the one exact kNN graph."""
+    from paper_1312_3062_amd import Index, knn_device, recall_at, synth
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    torch.cuda.set_device(0)
+    base = Index.build(X, w.graph_k, w.P, w.K, w.kmeans_iters, w.kmeans_seed, w.bridge_t, w.bridge_b)
+    G = base.export()["graph"]
+    del base
+    xd, qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    gt, _ = knn_device(xd, qd, w.k)
+    torch.cuda.synchronize()
+    gt = gt.cpu().numpy()
+    del xd
+    out = (torch.empty((len(Q), w.k), dtype=torch.int32, device="cuda"),
+           torch.empty((len(Q), w.k), dtype=torch.int32, device="cuda"))
+
+    def search(idx, T):
+        idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out)
+        torch.cuda.synchronize()
+        rec = recall_at(out[0].cpu().numpy(), gt, w.k)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for a, b in ev:
+            a.record()
+            idx.search_device(qd, w.k, T, queue_len=w.queue_len, out=out)
+            b.record()
+        torch.cuda.synchronize()
+        return rec, float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    rows = []
+    for P, K in ((2, 32), (2, 64), (2, 128), (2, 256), (4, 16), (4, 32), (4, 50)):
+        for t, b in ((1, 0), (1, 5), (100, 5)):
+            t0 = time.time()
+            idx = Index.build(X, w.graph_k, P, K, w.kmeans_iters, w.kmeans_seed, t, b, graph=G)
+            build_s = time.time() - t0
+            al = bridge_alpha(idx)
+            fixed = {T: search(idx, T) for T in (512, 1152, 2048)}
+            prev, hit = None, None
+            T = 128
+            while T <= 16384:
+                rec, ms = fixed[T] if T in fixed else search(idx, T)
+                if rec >= 0.9:
+                    hit = (T, rec, ms)
+                    break
+                prev, T = T, T * 2
+            if hit and prev:
+                step = max(16, prev // 8)
+                for T2 in range(prev + step, hit[0], step):
+                    rec, ms = search(idx, T2)
+                    if rec >= 0.9:
+                        hit = (T2, rec, ms)
+                        break
+            row = {"P": P, "K": K, "bridges": K ** P, "t": t, "b": b or "all", "reference": al["linked"],
+                   "alpha": round(al["alpha"], 5), "lists_nonempty": round(al["nonempty_share"], 5),
+                   "recall@10": {str(T): round(v[0], 4) for T, v in fixed.items()},
+                   "budget_at_0.9": hit[0] if hit else None,
+                   "qps_at_0.9": round(len(Q) / (hit[2] * 1e-3), 1) if hit else None,
+                   "build_s": round(build_s, 2)}
+            rows.append(row)
+            log(f"[sweep] P={P} K={K} t={t} b={b or 'all'}: #reference {al['linked']}, alpha {al['alpha']:.4f}, "
+                f"recall@10 at 512/1152/2048 {[row['recall@10'][k] for k in ('512', '1152', '2048')]}, "
+                f"T for 0.9: {row['budget_at_0.9']}, QPS {row['qps_at_0.9']}")
+            del idx
+    best = max((r["qps_at_0.9"] or 0.0) for r in rows)
+    line = {"metric": "QPS at recall@10>=0.9 per bridge rule and codebook, 1M x128 uint8", "value": best,
+            "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": None,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": w.name, "n": w.n, "queries": len(Q), "k": w.k, "queue_len": w.queue_len,
+                       "graph_k": w.graph_k},
+            "bridge_sweep": rows,
+            "paper_table_1": {"SIFT 1M, 4 x 50": {"reference": 715000, "alpha": 0.114},
+                              "GIST 1M, 4 x 50": {"reference": 599000, "alpha": 0.0959},
+                              "HOG 10M, 4 x 100": {"reference": 5730000, "alpha": 0.0573}}}
+    print(json.dumps(line), flush=True)
+
+
 def host_info() -> dict:
     """The host the oracle is timed on: logical CPUs, the ones this process may
     use, the CPU model and whether SMT is on."""
@@ -471,6 +552,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=800_000, help="query vectors the request streams draw")
     ap.add_argument("--bridge-t", type=int, default=-1, help="override the workload's bridges per vector (t)")
     ap.add_argument("--bridge-b", type=int, default=-1, help="override the workload's vectors per bridge (b; 0 = all)")
+    ap.add_argument("--sweep-bridges", action="store_true",
+                    help="sweep the bridge rule (t, b) and the codebooks (P, K) instead of the benchmark")
     ap.add_argument("--no-scale", action="store_true",
                     help="skip the 10M x 128 legs (uneven batch, mixed request stream)")
     ap.add_argument("--no-extra", action="store_true",
@@ -494,6 +577,9 @@ def main():
         import dataclasses
         w = dataclasses.replace(w, bridge_t=w.bridge_t if args.bridge_t < 0 else args.bridge_t,
                                 bridge_b=w.bridge_b if args.bridge_b < 0 else args.bridge_b)
+    if args.sweep_bridges:
+        bridge_sweep(w, args, torch)
+        return
     if w.variable_kT:
         bench_uneven(w, args, torch)
         return

@@ -820,15 +820,16 @@ k_search(SearchArgs a) {
         // look-ahead rows: lane l holds neighbour (l % R) of entry (l / R)
         uint32_t acn = ID_EMPTY;  // lane s < S: node id of entry s
         uint32_t ac_id = ID_EMPTY, ac_d = 0;
-        // visits of a look-ahead window: a lane's neighbour that was unvisited
-        // when its row was loaded keeps a distance-cache slot (ac_slot) until
-        // its row is expanded or a bridge with prefetched distances visits it.
-        // Expanding the row marks the visit with one atomic on that slot's
-        // flag (bridges with long lists set the flags of the ids they visit);
-        // the window's marks (pend) enter the visited set in one pass before
-        // the set is read again
+        // Visits: an id is visited if the visited set H holds it, or if the
+        // distance cache holds it with its visited flag set; for an id in the
+        // cache the flag decides.  A lane's neighbour that was unvisited when
+        // its row was loaded keeps its distance-cache slot (ac_slot) until its
+        // row is expanded: expanding the row marks the visit with one atomic
+        // on that slot's flag, and so does a bridge that visits an id the
+        // cache holds (the row then finds the flag set).  A visit of an id
+        // outside the cache goes to H; when the cache is cleared, its flagged
+        // ids move to H first.
         int ac_slot = -1;
-        bool pend = false;
         int t = 0;
         int dc_fill = 0;
         int st_rpop = 0, st_bpop = 0, st_bids = 0, st_gen = 0, st_rows = 0, st_spec = 0;
@@ -851,10 +852,21 @@ k_search(SearchArgs a) {
             if (__ballot(qa)) reg_merge1(Qv[0], qn, a.L, key, qa, lane, mrg);
         };
 
-        auto flush = [&](bool& full) {
+        // a bridge's list entry: visited unless the cache flags it or H holds
+        // it, marked visited either way; `cached` gets the distance the cache
+        // holds for it, or ID_EMPTY
+        auto visit_listed = [&](uint32_t vid, bool& full, uint32_t& cached) -> bool {
+            cached = ID_EMPTY;
+            if (vid == ID_EMPTY) return false;
+            const int ds = set_find(DK, a.dc_buckets, vid);
+            if (ds >= 0) {
+                const uint32_t old = atomicOr(&DV[ds], VISITED_FLAG);
+                cached = old & DIST_BITS;
+                return (old & VISITED_FLAG) == 0u;
+            }
             bool fresh = false;
-            if (pend && set_insert(H, a.hash_buckets, ac_id, fresh) < 0) full = true;
-            pend = false;
+            if (set_insert(H, a.hash_buckets, vid, fresh) < 0) full = true;
+            return fresh;
         };
 
         while (t < T) {
@@ -929,7 +941,6 @@ k_search(SearchArgs a) {
                     __syncthreads();
                     ++refills;
                     const bool with_dist = refills >= 2;
-                    if (a.prefetch && with_dist) flush(full);
 #pragma unroll 1
                     for (int u = 0; a.prefetch && u < GEN_BATCH * PRE_LIST / WAVE; ++u) {
                         const int sl = lane + u * WAVE;
@@ -1032,10 +1043,16 @@ k_search(SearchArgs a) {
                     asm("" : "+v"(col));
                     uint32_t nid = ID_EMPTY;
                     if (R > 0 && lane < ns * R) nid = a.G[int64_t(nd_l) * R + col];
-                    // while the rows load: the last window's visits enter the
-                    // visited set, and the distance cache is cleared when 5/8 full
-                    flush(full);
+                    // while the rows load: the distance cache is cleared when 5/8
+                    // full, its visit marks moving to the visited set first
                     if (dc_fill > dc_limit) {
+                        for (int c0 = 0; c0 < DW; c0 += WAVE) {
+                            const int i = c0 + lane;
+                            uint32_t vid = ID_EMPTY;
+                            if (i < DW && (DV[i] & VISITED_FLAG)) vid = DK[i];
+                            bool fresh = false;
+                            if (vid != ID_EMPTY && set_insert(H, a.hash_buckets, vid, fresh) < 0) full = true;
+                        }
                         for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
                         dc_fill = 0;
                         lds_wave_order();
@@ -1058,7 +1075,10 @@ k_search(SearchArgs a) {
                     dc_fill += m;
                     if constexpr (COUNT) st_rows += m;
                     __syncthreads();
-                    ac_d = known ? (need ? gdist : (DV[slot] & DIST_BITS)) : 0u;
+                    // an id the cache already held may have been visited since
+                    const uint32_t dv = known && !need ? DV[slot] : 0u;
+                    if (dv & VISITED_FLAG) known = false;
+                    ac_d = known ? (need ? gdist : (dv & DIST_BITS)) : 0u;
                     ac_slot = known ? slot : -1;
                     hit = 1;  // entry 0 is the queue head
                 }
@@ -1072,7 +1092,6 @@ k_search(SearchArgs a) {
                 bool white = false;
                 if (inrow && ac_slot >= 0) white = (atomicOr(&DV[ac_slot], VISITED_FLAG) & VISITED_FLAG) == 0u;
                 if (inrow) ac_slot = -1;  // the row is expanded
-                pend = pend || white;
                 const uint64_t wm = __ballot(white);
                 take = min(int(__popcll(wm)), T - t);
                 r = lanes_below(wm);
@@ -1090,32 +1109,19 @@ k_search(SearchArgs a) {
                     st_bids += len;
                 }
                 id = lane < len ? pre_id[e * PRE_LIST + lane] : ID_EMPTY;
-                flush(full);
-                bool white = false;
-                if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
+                uint32_t cached = ID_EMPTY;
+                const bool white = visit_listed(id, full, cached);
                 const uint64_t wm = __ballot(white);
                 take = min(int(__popcll(wm)), T - t);
                 r = lanes_below(wm);
                 ev = white && r < take;
                 if ((dist_mask >> e) & 1u) {
                     dist = pre_d[e * PRE_LIST + lane];  // measured ahead: white then, so not visited then
-                    // the window's unexpanded rows see these (at most 8) visits:
-                    // lanes holding one of the ids give up their cache slot
-                    uint64_t evm = __ballot(ev);
-                    while (evm) {
-                        const int j = __builtin_ctzll(evm);
-                        evm &= evm - 1;
-                        if (ac_id == uint32_t(__builtin_amdgcn_readlane(int(id), j))) ac_slot = -1;
-                    }
                 } else {
-                    // an evaluated id with a cache slot flags it, so that the
-                    // rows of the current window see the visit
-                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
-                    const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
-                    const bool miss = ev && slot < 0;
+                    const bool miss = ev && cached == ID_EMPTY;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
-                    dist = slot >= 0 ? cached : gdist;
+                    dist = cached != ID_EMPTY ? cached : gdist;
                 }
             } else {
                 // ---- a bridge with a long list: walked from global memory
@@ -1130,24 +1136,21 @@ k_search(SearchArgs a) {
                 // lists longer than a wave are walked in chunks; every chunk but
                 // the one that ends the list or the budget is merged here, that
                 // one below
-                flush(full);
                 const uint32_t* list = graph_only ? a.seeds : a.bids;
                 for (int c0 = 0;; c0 += WAVE) {
                     const int j = c0 + lane;
                     id = j < len ? list[base + j] : ID_EMPTY;
                     if (id >= uint32_t(n)) id = ID_EMPTY;  // a seed outside [0, n) is skipped
-                    bool white = false;
-                    if (id != ID_EMPTY && set_insert(H, a.hash_buckets, id, white) < 0) full = true;
+                    uint32_t cached = ID_EMPTY;
+                    const bool white = visit_listed(id, full, cached);
                     const uint64_t wm = __ballot(white);
                     take = min(int(__popcll(wm)), T - t);
                     r = lanes_below(wm);
                     ev = white && r < take;
-                    const int slot = ev ? set_find(DK, a.dc_buckets, id) : -1;
-                    const uint32_t cached = slot >= 0 ? (atomicOr(&DV[slot], VISITED_FLAG) & DIST_BITS) : 0u;
-                    const bool miss = ev && slot < 0;
+                    const bool miss = ev && cached == ID_EMPTY;
                     const uint32_t gdist = gather_need<MODE, NC16>(a, qv, qq, id, miss, gid, gd, lane);
                     if constexpr (COUNT) st_rows += __popcll(__ballot(miss));
-                    dist = slot >= 0 ? cached : gdist;
+                    dist = cached != ID_EMPTY ? cached : gdist;
                     if (c0 + WAVE >= len || t + take >= T) break;
                     offer(make_key(dist, id), ev);
                     t += take;
