@@ -51,6 +51,8 @@ def load(path: str):
     L.orc_search_ex.argtypes = [vp, i64, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp, i64,
                                 vp, vp, i32, i32, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]
     L.orc_bf16_round.argtypes = [vp, i64, vp]
+    L.orc_pq_encode.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
+    L.orc_ivf_adc.argtypes = [vp, i64, i32, vp, vp, vp, vp, i32, i32, vp, vp, i32, i64, i32, vp, vp, vp]
     return L
 
 
@@ -219,3 +221,41 @@ def build_index(X: np.ndarray, P: int, K: int, R: int, iters: int, seed: int, t:
     g, _ = knn_graph_rows(X, np.arange(n), R) if R > 0 else (np.zeros((n, 0), np.int32), None)
     off, ids, _ = bridge_graph(X, cb, t, b)
     return cb, g.astype(np.uint32), off, ids
+
+
+def pq_encode(R: np.ndarray, codebooks: np.ndarray, want_gap: bool = False):
+    """Residual codes (Sec. 5): per subspace the nearest codeword of
+    codebooks (m, K, d/m) float32, ties to the smaller index.  R (n, d) is
+    taken in double precision.  With want_gap also the second-best minus the
+    best squared distance per code."""
+    R = np.ascontiguousarray(R, np.float64)
+    cb = np.ascontiguousarray(codebooks, np.float32)
+    n, d = R.shape
+    m, K, _ = cb.shape
+    codes = np.empty((n, m), np.uint8)
+    gap = np.empty((n, m), np.float64) if want_gap else None
+    lib().orc_pq_encode(_p(R), n, d, m, K, _p(cb), _p(codes), _p(gap))
+    return (codes, gap) if want_gap else codes
+
+
+def ivf_adc(Q: np.ndarray, centres: np.ndarray, list_off: np.ndarray, list_ids: np.ndarray, codes: np.ndarray,
+            codebooks: np.ndarray, lists: np.ndarray, L: int, k: int, want_count: bool = False):
+    """Graph-D-ADC re-ranking (Sec. 5): each query's lists (nq, W) in
+    visiting order (-1 skipped), candidates cut at exactly L, ranked by
+    |q - c - r|^2 then id.  Returns (ids (nq, k) int32, dists (nq, k))."""
+    Q = np.ascontiguousarray(Q, np.uint8)
+    centres = np.ascontiguousarray(centres, np.uint8)
+    list_off = np.ascontiguousarray(list_off, np.uint32)
+    list_ids = np.ascontiguousarray(list_ids, np.uint32)
+    codes = np.ascontiguousarray(codes, np.uint8)
+    cb = np.ascontiguousarray(codebooks, np.float32)
+    lists = np.ascontiguousarray(lists, np.int32)
+    nq, d = Q.shape
+    m, K, _ = cb.shape
+    W = lists.shape[1]
+    ids = np.empty((nq, k), np.int32)
+    dd = np.empty((nq, k), np.float64)
+    cnt = np.empty(nq, np.int64)
+    lib().orc_ivf_adc(_p(Q), nq, d, _p(centres), _p(list_off), _p(list_ids), _p(codes), m, K, _p(cb), _p(lists),
+                      W, int(L), k, _p(ids), _p(dd), _p(cnt))
+    return (ids, dd, cnt) if want_count else (ids, dd)

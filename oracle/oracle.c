@@ -685,3 +685,104 @@ void orc_search(const void* X, int64_t n, int d, int dtype, int P, int K, const 
     orc_search_ex(X, n, d, dtype, P, K, codebooks, R, G, off, ids, Qv, nq, ks, Ts, kmax, L, 0, 0, 1, NULL, 0,
                   out_ids, out_d, trace, tmax, stats);
 }
+
+/* ------------------------------------------------------------------ */
+/* Graph-D-ADC (Sec. 5, the billion-scale comparison): inverted lists   */
+/* whose coarse centres are found by the graph search, each vector      */
+/* stored as the product-quantised residual to its list's centre.       */
+/* Readings: a residual subvector's code is its nearest codeword (ties  */
+/* to the smaller index); a query visits its lists by increasing centre */
+/* distance, each list in the stored order, and the candidate list is   */
+/* cut at exactly L vectors, inside a list if need be; candidates are   */
+/* ranked by the asymmetric distance |q - c - r|^2 (c the list's        */
+/* centre, r the codewords of the vector's code concatenated) and then  */
+/* by id.                                                               */
+/* ------------------------------------------------------------------ */
+
+/* Codes of n residuals (n x d, double) under m subspaces of K float
+ * codewords each (codebooks m x K x d/m).  gap (optional, n x m) receives
+ * the second-best minus the best squared distance per subvector. */
+void orc_pq_encode(const double* Rv, int64_t n, int d, int m, int K, const float* cb, uint8_t* codes,
+                   double* gap) {
+    const int ds = d / m;
+    for (int64_t i = 0; i < n; i++)
+        for (int p = 0; p < m; p++) {
+            int best = 0;
+            double bd = 0.0, second = INFINITY;
+            for (int j = 0; j < K; j++) {
+                double s = 0.0;
+                for (int e = 0; e < ds; e++) {
+                    const double t = Rv[i * d + p * ds + e] - (double)cb[((int64_t)p * K + j) * ds + e];
+                    s += t * t;
+                }
+                if (j == 0 || s < bd) {
+                    if (j > 0) second = bd;
+                    bd = s;
+                    best = j;
+                } else if (s < second) {
+                    second = s;
+                }
+            }
+            codes[i * m + p] = (uint8_t)best;
+            if (gap) gap[i * m + p] = second - bd;
+        }
+}
+
+typedef struct {
+    double dist;
+    int32_t id;
+} orc_cand;
+
+static int orc_cand_cmp(const void* a, const void* b) {
+    const orc_cand* x = (const orc_cand*)a;
+    const orc_cand* y = (const orc_cand*)b;
+    if (x->dist != y->dist) return x->dist < y->dist ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+/* The re-ranking of Sec. 5 for nq byte queries.  lists (nq x W) names each
+ * query's lists in visiting order (-1 entries are skipped); list j holds
+ * positions list_off[j] .. list_off[j+1] of list_ids (vector ids) and codes
+ * (m bytes per position).  out_ids / out_d are nq x k, ascending by
+ * (distance, id), padded with -1 / +infinity.  cand_count (optional, nq)
+ * receives the number of candidates ranked. */
+void orc_ivf_adc(const uint8_t* Q, int64_t nq, int d, const uint8_t* centres, const uint32_t* list_off,
+                 const uint32_t* list_ids, const uint8_t* codes, int m, int K, const float* cb, const int32_t* lists,
+                 int W, int64_t L, int k, int32_t* out_ids, double* out_d, int64_t* cand_count) {
+    const int ds = d / m;
+    int64_t cap = 0;
+    orc_cand* cand = NULL;
+    for (int64_t qi = 0; qi < nq; qi++) {
+        const uint8_t* q = Q + qi * d;
+        int64_t c = 0;
+        for (int w = 0; w < W && c < L; w++) {
+            const int32_t l = lists[qi * W + w];
+            if (l < 0) continue;
+            for (uint32_t pos = list_off[l]; pos < list_off[l + 1] && c < L; pos++) {
+                if (c == cap) {
+                    cap = cap ? 2 * cap : 1024;
+                    cand = (orc_cand*)realloc(cand, sizeof(orc_cand) * (size_t)cap);
+                }
+                double s = 0.0;
+                for (int p = 0; p < m; p++) {
+                    const float* r = cb + ((int64_t)p * K + codes[(int64_t)pos * m + p]) * ds;
+                    for (int e = 0; e < ds; e++) {
+                        const int j = p * ds + e;
+                        const double t = (double)q[j] - (double)centres[(int64_t)l * d + j] - (double)r[e];
+                        s += t * t;
+                    }
+                }
+                cand[c].dist = s;
+                cand[c].id = (int32_t)list_ids[pos];
+                c++;
+            }
+        }
+        if (c > 1) qsort(cand, (size_t)c, sizeof(orc_cand), orc_cand_cmp);
+        for (int i = 0; i < k; i++) {
+            out_ids[qi * k + i] = i < c ? cand[i].id : -1;
+            out_d[qi * k + i] = i < c ? cand[i].dist : INFINITY;
+        }
+        if (cand_count) cand_count[qi] = c;
+    }
+    free(cand);
+}

@@ -542,3 +542,93 @@ def test_seeded_graph_search_closed_forms():
     eid, ed = literal.brute_knn(X, Q, 10)
     np.testing.assert_array_equal(rid, eid)
     np.testing.assert_array_equal(rd, ed)
+
+
+# ---------------------------------------------------------------- Graph-D-ADC (Sec. 5)
+
+def _adc_example():
+    """Worked by hand.  d = 4, two subspaces of two codewords each.
+    List 0 (centre 10,10,10,10): ids 2 (code 1,0) and 5 (code 0,1);
+    list 1 (centre 0,0,0,0): id 7 (code 1,1); list 2 (centre 5,5,5,5): ids 9
+    and 4, both code 0,0.  Query 11,12,9,10:
+      id 2: q - c - r = (0, 0, -1, 0)        -> 1
+      id 5: q - c - r = (1, 2, 2, -0.5)      -> 9.25
+      id 7: q - c - r = (10, 10, 12, 9.5)    -> 434.25
+      ids 9 and 4: q - c = (6, 7, 4, 5)      -> 126 (a tie: 4 before 9)"""
+    centres = np.array([[10, 10, 10, 10], [0, 0, 0, 0], [5, 5, 5, 5]], np.uint8)
+    cb = np.array([[[0, 0], [1, 2]], [[0, 0], [-3, 0.5]]], np.float32)
+    list_off = np.array([0, 2, 3, 5], np.uint32)
+    list_ids = np.array([2, 5, 7, 9, 4], np.uint32)
+    codes = np.array([[1, 0], [0, 1], [1, 1], [0, 0], [0, 0]], np.uint8)
+    q = np.array([[11, 12, 9, 10]], np.uint8)
+    return q, centres, list_off, list_ids, codes, cb
+
+
+@pytest.mark.parametrize("order,L,k,ids,dists,count", [
+    ([0, 1, 2], 5, 5, [2, 5, 4, 9, 7], [1, 9.25, 126, 126, 434.25], 5),
+    ([1, 0], 2, 3, [2, 7, -1], [1, 434.25, np.inf], 2),          # list 0 cut after its first vector
+    ([2, -1, 0], 3, 3, [2, 4, 9], [1, 126, 126], 3),             # -1 skipped, cut inside list 0
+    ([0, 1, 2], 0, 2, [-1, -1], [np.inf, np.inf], 0),
+    ([0, 1, 2], 100, 2, [2, 5], [1, 9.25], 5),
+])
+def test_ivf_adc_hand_example(order, L, k, ids, dists, count):
+    q, centres, off, lids, codes, cb = _adc_example()
+    got, gd, cnt = oracle.ivf_adc(q, centres, off, lids, codes, cb, np.array([order]), L, k, want_count=True)
+    assert got[0].tolist() == ids
+    np.testing.assert_array_equal(gd[0], np.array(dists, np.float64))
+    assert cnt[0] == count
+
+
+def test_pq_encode_matches_bruteforce_argmin():
+    """Nearest codeword per subspace, first index on ties (numpy's argmin),
+    with duplicated codewords planted so that ties occur."""
+    rng = np.random.default_rng(11)
+    n, d, m, K = 50, 8, 4, 16
+    R = rng.integers(-6, 7, size=(n, d)).astype(np.float64)
+    cb = rng.integers(-6, 7, size=(m, K, d // m)).astype(np.float32)
+    cb[0, 9] = cb[0, 3]
+    cb[2, 15] = cb[2, 0]
+    R[:5, 0:2] = cb[0, 3]                 # exactly on the duplicated codeword
+    codes, gap = oracle.pq_encode(R, cb, want_gap=True)
+    ds = d // m
+    for p in range(m):
+        D = ((R[:, None, p * ds:(p + 1) * ds] - cb[p][None].astype(np.float64)) ** 2).sum(-1)
+        np.testing.assert_array_equal(codes[:, p], D.argmin(1))
+        S = np.sort(D, 1)
+        np.testing.assert_array_equal(gap[:, p], S[:, 1] - S[:, 0])
+    assert (codes[:5, 0] == 3).all() and (gap[:5, 0] == 0).all()
+
+
+@pytest.mark.parametrize("L", [10_000, 37])
+def test_ivf_adc_with_exact_codes_is_exact_knn(L):
+    """Codebooks holding every residual subvector reproduce each vector
+    exactly, so with every list visited and no cut the re-ranking is the
+    brute-force k-nearest-neighbour list by (distance, id); with a cut it is
+    the brute-force list over the first L vectors in list order."""
+    rng = np.random.default_rng(12)
+    n, d, m, K, C, k = 60, 8, 2, 64, 3, 10
+    X = rng.integers(0, 12, size=(n, d)).astype(np.uint8)
+    centres = X[[4, 17, 33]]
+    Dc = ((X[:, None, :].astype(np.int64) - centres[None].astype(np.int64)) ** 2).sum(-1)
+    assign = Dc.argmin(1)
+    R = X.astype(np.float64) - centres[assign].astype(np.float64)
+    ds = d // m
+    cb = rng.integers(-12, 13, size=(m, K, ds)).astype(np.float32)
+    for p in range(m):
+        slots = rng.permutation(K)[:n]
+        cb[p, slots] = R[:, p * ds:(p + 1) * ds]
+    codes_v = oracle.pq_encode(R, cb)
+    for p in range(m):
+        np.testing.assert_array_equal(cb[p, codes_v[:, p]].astype(np.float64), R[:, p * ds:(p + 1) * ds])
+    list_ids = np.concatenate([np.flatnonzero(assign == j) for j in range(C)]).astype(np.uint32)
+    list_off = np.concatenate([[0], np.cumsum(np.bincount(assign, minlength=C))]).astype(np.uint32)
+    codes = codes_v[list_ids]
+    Q = rng.integers(0, 12, size=(7, d)).astype(np.uint8)
+    order = np.tile(np.array([[2, 0, 1]], np.int32), (len(Q), 1))
+    ids, dd = oracle.ivf_adc(Q, centres, list_off, list_ids, codes, cb, order, L, k)
+    pool = np.concatenate([list_ids[list_off[j]:list_off[j + 1]] for j in (2, 0, 1)])[:L].astype(np.int64)
+    for qi in range(len(Q)):
+        exact = ((X[pool].astype(np.int64) - Q[qi].astype(np.int64)) ** 2).sum(1)
+        o = np.lexsort((pool, exact))[:k]
+        np.testing.assert_array_equal(ids[qi], pool[o])
+        np.testing.assert_array_equal(dd[qi], exact[o].astype(np.float64))

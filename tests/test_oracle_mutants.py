@@ -8,6 +8,7 @@ GPU or the committed oracle library.
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
@@ -36,6 +37,21 @@ MUTANTS = [
     ("only the first seed measured", "        int64_t alen = use_bridges ? 0 : nseeds;",
      "        int64_t alen = use_bridges ? 0 : (nseeds > 1 ? 1 : nseeds);",
      [("test_seeded_graph_search_matches_literal", (2,))]),
+    ("ADC residual added, not subtracted",
+     "const double t = (double)q[j] - (double)centres[(int64_t)l * d + j] - (double)r[e];",
+     "const double t = (double)q[j] - (double)centres[(int64_t)l * d + j] + (double)r[e];",
+     [("test_ivf_adc_hand_example", ([0, 1, 2], 5, 5, [2, 5, 4, 9, 7], [1, 9.25, 126, 126, 434.25], 5)),
+      ("test_ivf_adc_with_exact_codes_is_exact_knn", (10_000,))]),
+    ("candidate list cut only at a list's end",
+     "for (uint32_t pos = list_off[l]; pos < list_off[l + 1] && c < L; pos++) {",
+     "for (uint32_t pos = list_off[l]; pos < list_off[l + 1]; pos++) {",
+     [("test_ivf_adc_hand_example", ([1, 0], 2, 3, [2, 7, -1], [1, 434.25, np.inf], 2)),
+      ("test_ivf_adc_with_exact_codes_is_exact_knn", (37,))]),
+    ("ADC ties to the larger id", "    return (x->id > y->id) - (x->id < y->id);",
+     "    return (x->id < y->id) - (x->id > y->id);",
+     [("test_ivf_adc_hand_example", ([0, 1, 2], 5, 5, [2, 5, 4, 9, 7], [1, 9.25, 126, 126, 434.25], 5))]),
+    ("residual codes tie to the larger codeword", "                if (j == 0 || s < bd) {",
+     "                if (j == 0 || s <= bd) {", [("test_pq_encode_matches_bruteforce_argmin", ())]),
 ]
 
 
