@@ -501,6 +501,70 @@ def scan_overhead_leg(idx, w, X, Q, torch, visited=10_000):
             "overhead_us_per_query": round(per_q(s_ms - l_ms), 3), "ratio": round(s_ms / max(l_ms, 1e-9), 2)}
 
 
+def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 30_000, 100_000), pq_iters=4,
+                    assign_budget=256, seed=7):
+    """Sec. 5 (Table 2's protocol on synthetic data): inverted lists over
+    `lists` coarse centres (a seeded sample of the vectors, about 163 vectors
+    a list as 1B / 6M in the paper), each vector assigned by the graph search
+    over the centres, its residual product-quantised into m bytes; a query
+    visits its nearest lists until L candidates and re-ranks them by the
+    asymmetric distance.  R@T: share of queries whose true nearest neighbour
+    is within the first T re-ranked candidates."""
+    from paper_1312_3062_amd.ivf import Ivf
+    qd = torch.from_numpy(Q).cuda()
+    nq = len(Q)
+    out = []
+    for m in ms:
+        t0 = time.time()
+        ivf = Ivf.build(X, lists=lists, pq_m=m, pq_iters=pq_iters, assign_budget=assign_budget, seed=seed,
+                        graph_k=16, P=2, K=64, kmeans_iters=4, bridge_t=1, bridge_b=5, centre_seed=seed)
+        torch.cuda.synchronize()
+        build_s = time.time() - t0
+        off = ivf.export()["list_off"].astype(np.int64)
+        sizes = np.diff(off)
+        cidx = ivf.centres_index()
+        log(f"[adc] m={m}: built in {build_s:.1f}s, {lists} lists of {sizes.mean():.0f} vectors on average "
+            f"(largest {sizes.max()}, empty {int((sizes == 0).sum())})")
+        for L in lengths:
+            W = int(min(1024, np.ceil(1.5 * L / max(1.0, sizes.mean()))))
+            Tc = max(256, 2 * W)
+
+            def ms_of(fn, reps=3):
+                fn()
+                torch.cuda.synchronize()
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(reps)]
+                for a, b in ev:
+                    a.record()
+                    fn()
+                    b.record()
+                torch.cuda.synchronize()
+                return float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+            res = {}
+            total_ms = ms_of(lambda: res.update(r=ivf.search_device(qd, 100, W, Tc, L)))
+            lists_ms = ms_of(lambda: cidx.search_device(qd, W, Tc))
+            ids = res["r"][0].cpu().numpy()
+            gl, _ = cidx.search_device(qd, W, Tc)
+            gl = gl.cpu().numpy().astype(np.int64)
+            cand = np.minimum(np.where(gl >= 0, sizes[np.maximum(gl, 0)], 0).sum(1), L)
+            hit = ids == gt1[:, None]
+            rec = {f"R@{t}": round(float(hit[:, :t].any(1).mean()), 4) for t in (1, 10, 100)}
+            adc_ms = total_ms - lists_ms
+            adc_bytes = float(cand.sum()) * (m + 8)
+            row = {"m": m, "L": L, "lists_visited": W, "centre_budget": Tc,
+                   "candidates_per_query": round(float(cand.mean()), 1), **rec,
+                   "batch_ms": round(total_ms, 3), "list_search_ms": round(lists_ms, 3), "adc_ms": round(adc_ms, 3),
+                   "qps": round(nq / (total_ms * 1e-3), 1), "us_per_query": round(total_ms * 1e3 / nq, 3),
+                   "adc_GBps": round(adc_bytes / max(adc_ms, 1e-6) / 1e6, 1), "build_s": round(build_s, 1)}
+            log(f"[adc] m={m} L={L}: lists {W}, {row['candidates_per_query']:.0f} candidates, {rec}, "
+                f"{total_ms:.2f} ms per {nq} queries (lists {lists_ms:.2f}), {row['qps']:.0f} QPS")
+            out.append(row)
+        ivf.close()
+    return {"lists": lists, "n": len(X), "queries": nq, "pq_iters": pq_iters, "assign_budget": assign_budget,
+            "results": out}
+
+
 def oracle_all_cores(oracle, X, parts, Q, sample, passes, w, T, gpu_ids):
     """The same oracle sample spread over the host's cores: one thread per
     slice of the queries (the C oracle runs outside the interpreter lock),
@@ -558,6 +622,7 @@ def main():
                     help="skip the 10M x 128 legs (uneven batch, mixed request stream)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the graph search without bridges and the linear-scan overhead legs")
+    ap.add_argument("--adc-only", action="store_true", help="run the Graph-D-ADC leg alone")
     ap.add_argument("--copy-probe", action="store_true",
                     help="end with a copy-like kernel over 1 GiB (calibrates hardware traffic counters)")
     args = ap.parse_args()
@@ -582,6 +647,14 @@ def main():
         return
     if w.variable_kT:
         bench_uneven(w, args, torch)
+        return
+    if args.adc_only:
+        X, Q = synth.base_vectors(w), synth.queries(w)
+        xd, qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+        gt, _ = knn_device(xd, qd, 1)
+        torch.cuda.synchronize()
+        del xd
+        print(json.dumps({"graph_d_adc": graph_d_adc_leg(X, Q, gt.cpu().numpy()[:, 0], torch)}), flush=True)
         return
     t0 = time.time()
     X = synth.base_vectors(w)
@@ -721,10 +794,15 @@ def main():
             serving["mixed_k_budget"] = serving_leg(idx, w, args, gt_fn)
         del xd2
 
-    graph_leg = scan_leg = None
+    graph_leg = scan_leg = adc_leg = None
     if not args.no_extra and X.dtype == np.uint8:
         graph_leg = [graph_search_leg(idx, w, Q, gt, torch, sweep, seeds_count=c) for c in (16, 256)]
         scan_leg = scan_overhead_leg(idx, w, X, Q, torch)
+        try:
+            adc_leg = graph_d_adc_leg(X, Q, gt[:, 0], torch)
+        except Exception as e:  # reported in the line; the headline above stands
+            log(f"[bench] Graph-D-ADC leg failed: {e!r}")
+            adc_leg = {"error": repr(e)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -784,6 +862,7 @@ def main():
         "precision": precision,
         "graph_search_without_bridges": graph_leg,
         "overhead_vs_linear_scan": scan_leg,
+        "graph_d_adc": adc_leg,
     }
     if not args.no_scale and X.dtype == np.uint8 and not overridden:
         # the 10M x 128 workload: its uneven batch (a second roofline figure,

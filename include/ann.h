@@ -408,6 +408,77 @@ int ann_server_get_info(const ann_server* server, ann_server_info* info);
 /* Wait for the micro-batches in flight, then free everything. */
 void ann_server_destroy(ann_server* server);
 
+/* ------------------------------------------------------------------ */
+/* Graph-D-ADC: the search as the inverted-list lookup of IVFADC       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * The paper's billion-scale system (Sec. 5): a vocabulary of coarse centres
+ * indexed by the augmented neighborhood graph; each vector belongs to the
+ * inverted list of the centre the graph search returns for it (k = 1), and
+ * its residual to that centre is encoded by product quantisation (pq_m
+ * subspaces of d / pq_m dims, 256 codewords each, one byte per subspace).
+ * A query searches the centres for its nearest lists and re-ranks their
+ * vectors by the asymmetric distance |q - c - r|^2, r the residual's
+ * codewords concatenated.
+ */
+typedef struct ann_ivf ann_ivf;
+
+typedef struct {
+    uint32_t struct_size;       /* sizeof(ann_ivf_params) */
+    int32_t lists;              /* C coarse centres: a seeded sample of the vectors (the first C of a
+                                   SplitMix64-driven Fisher-Yates shuffle of [0, n) from `seed`) */
+    int32_t pq_m;               /* bytes per vector: 8 or 16, dividing d */
+    int32_t pq_iters;           /* k-means iterations of the residual codebooks (initial codewords: the
+                                   residuals of 256 rows drawn the same way from seed + 1) */
+    int32_t assign_budget;      /* budget of the search assigning each vector to its list */
+    int32_t reserved;           /* must be 0 */
+    uint64_t seed;
+    ann_build_params centres;   /* the augmented index over the centres */
+} ann_ivf_params;
+
+typedef struct {
+    int64_t n;
+    int32_t d, lists, pq_m, reserved;
+    int64_t device_bytes;       /* lists, codes, the per-vector constants and codebooks (the centres'
+                                   index excluded) */
+} ann_ivf_info;
+
+/*
+ * Build from host data (n x d uint8, 256 <= n < 2^31) on the current device.
+ * Errors: ANN_EINVAL, ANN_ENOMEM, ANN_EDEVICE, ANN_ERESOURCE (a vector found
+ * no list within assign_budget).
+ */
+int ann_ivf_build(const void* data, int64_t n, int32_t d, const ann_ivf_params* params, ann_ivf** out);
+
+int ann_ivf_get_info(const ann_ivf* ivf, ann_ivf_info* info);
+
+/* The augmented index over the centres (owned by the ivf). */
+const ann_index* ann_ivf_centres(const ann_ivf* ivf);
+
+/*
+ * Host copies (each pointer may be null): centres lists x d; list_off
+ * lists + 1 (list j holds positions list_off[j] .. list_off[j+1]); list_ids
+ * n vector ids in list order (a list in increasing id); codes n x pq_m in
+ * list order; pq_codebooks pq_m x 256 x (d / pq_m) float.
+ */
+int ann_ivf_export(const ann_ivf* ivf, uint8_t* centres, uint32_t* list_off, uint32_t* list_ids, uint8_t* codes,
+                   float* pq_codebooks);
+
+/*
+ * For each query: the `lists` nearest centres by the graph search (budget
+ * centre_budget, queue length 64), then the vectors of those lists, lists by
+ * increasing centre distance and each list in its order, up to `candidates`
+ * of them (the scan stops mid-list when they are reached), ranked by the
+ * asymmetric distance (fp32).  d_ids nq x k int32, d_dists nq x k float,
+ * ascending by (distance, id), padded with -1 / +infinity.  1 <= k <= 1024,
+ * 1 <= lists <= 1024.  Asynchronous on `stream`.
+ */
+int ann_ivf_search_device(const ann_ivf* ivf, const void* d_queries, int64_t nq, int32_t k, int32_t lists,
+                          int32_t centre_budget, int32_t candidates, int32_t* d_ids, float* d_dists, void* stream);
+
+void ann_ivf_free(ann_ivf* ivf);
+
 /*
  * Query preprocessing alone (Sec. 4.2): for each query the P x K squared
  * distances to the codewords, each subspace sorted ascending by

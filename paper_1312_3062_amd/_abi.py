@@ -49,6 +49,17 @@ class ServerInfo(C.Structure):
                 ("device_bytes", C.c_int64)]
 
 
+class IvfParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("lists", C.c_int32), ("pq_m", C.c_int32), ("pq_iters", C.c_int32),
+                ("assign_budget", C.c_int32), ("reserved", C.c_int32), ("seed", C.c_uint64),
+                ("centres", BuildParams)]
+
+
+class IvfInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("lists", C.c_int32), ("pq_m", C.c_int32),
+                ("reserved", C.c_int32), ("device_bytes", C.c_int64)]
+
+
 class AnnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"[{status}] {msg}")
@@ -86,6 +97,12 @@ SIGNATURES = {
     "ann_server_drain": (_i32, [_vp]),
     "ann_server_get_info": (_i32, [_vp, C.POINTER(ServerInfo)]),
     "ann_server_destroy": (None, [_vp]),
+    "ann_ivf_build": (_i32, [_vp, _i64, _i32, C.POINTER(IvfParams), C.POINTER(_vp)]),
+    "ann_ivf_get_info": (_i32, [_vp, C.POINTER(IvfInfo)]),
+    "ann_ivf_centres": (_vp, [_vp]),
+    "ann_ivf_export": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "ann_ivf_search_device": (_i32, [_vp, _vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "ann_ivf_free": (None, [_vp]),
     "ann_query_tables_device": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp]),
     "ann_knn_device": (_i32, [_vp, _i64, _i32, _i32, _vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "ann_last_error": (_cp, []),

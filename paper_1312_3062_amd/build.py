@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libann.so")
-SOURCES = ["abi.hip", "build.hip", "knn.hip", "search.hip", "noalloc.hip", "server.hip"]
+SOURCES = ["abi.hip", "build.hip", "knn.hip", "search.hip", "noalloc.hip", "server.hip", "ivf.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

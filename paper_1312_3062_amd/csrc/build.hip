@@ -413,6 +413,22 @@ int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
     return ANN_OK;
 }
 
+int kmeans_assign_subspace(const uint8_t* X, int64_t n, int d, bool f32, int ds, int p, int K, const void* cb_p,
+                           int32_t* assign, hipStream_t s) {
+    const int esz = f32 ? 4 : 1;
+    const int kc = std::max(1, std::min(K, KM_CHUNK_BYTES / (ds * esz)));
+    const int lds_assign = ((kc * ds * esz + 15) & ~15) + kc * 4;
+    const int64_t grid = ceil_div(n, KM_THREADS);
+    if (f32)
+        hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s, X, n, d, ds,
+                           p, K, cb_p, kc, assign);
+    else
+        hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s, X, n, d, ds,
+                           p, K, cb_p, kc, assign);
+    ANN_HIP_CHECK(hipGetLastError());
+    return ANN_OK;
+}
+
 int build_bridge_graph(ann_index* idx, int t, int b, hipStream_t s) {
     const bool f = idx->dtype == ANN_F32;
     const int64_t n = idx->n, nb = idx->nb;

@@ -64,6 +64,10 @@ int launch_knn(const void* d_x, int64_t n, int d, int dtype, const void* d_q, in
                int32_t* d_ids, void* d_dists, hipStream_t s);
 int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s);
 int build_bridge_graph(ann_index* idx, int t, int b, hipStream_t s);
+// the k-means assignment step for subspace p alone (nearest of K codewords,
+// ties to the smaller one): cb_p holds that subspace's K x ds codewords
+int kmeans_assign_subspace(const uint8_t* X, int64_t n, int d, bool f32, int ds, int p, int K, const void* cb_p,
+                           int32_t* assign, hipStream_t s);
 int make_bf16_copy(ann_index* idx, hipStream_t s);
 
 // SplitMix64 and the seeded choice of the initial k-means rows (host side).
