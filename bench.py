@@ -508,8 +508,10 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
     a list as 1B / 6M in the paper), each vector assigned by the graph search
     over the centres, its residual product-quantised into m bytes; a query
     visits its nearest lists until L candidates and re-ranks them by the
-    asymmetric distance.  R@T: share of queries whose true nearest neighbour
-    is within the first T re-ranked candidates."""
+    asymmetric distance.  The centres' index: kNN graph of 16, two subspaces
+    of 16 codewords, every centre linked from its nearest bridge; the lists
+    come from a search with budget 4W for W lists.  R@T: share of queries
+    whose true nearest neighbour is within the first T re-ranked candidates."""
     from paper_1312_3062_amd.ivf import Ivf
     qd = torch.from_numpy(Q).cuda()
     nq = len(Q)
@@ -517,7 +519,7 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
     for m in ms:
         t0 = time.time()
         ivf = Ivf.build(X, lists=lists, pq_m=m, pq_iters=pq_iters, assign_budget=assign_budget, seed=seed,
-                        graph_k=16, P=2, K=64, kmeans_iters=4, bridge_t=1, bridge_b=5, centre_seed=seed)
+                        graph_k=16, P=2, K=16, kmeans_iters=4, bridge_t=1, bridge_b=0, centre_seed=seed)
         torch.cuda.synchronize()
         build_s = time.time() - t0
         off = ivf.export()["list_off"].astype(np.int64)
@@ -527,7 +529,7 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
             f"(largest {sizes.max()}, empty {int((sizes == 0).sum())})")
         for L in lengths:
             W = int(min(1024, np.ceil(1.5 * L / max(1.0, sizes.mean()))))
-            Tc = max(256, 2 * W)
+            Tc = max(256, 4 * W)
 
             def ms_of(fn, reps=3):
                 fn()

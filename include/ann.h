@@ -7,7 +7,9 @@
  *
  * Conventions shared by every entry point
  * ----------------------------------------
- *  - Every call returns ann_status: ANN_OK (0) or a negative error code.  No
+ *  - Every call declared to return int returns a value of ann_status:
+ *    ANN_OK (0) or a negative error code (int rather than the enum type, so
+ *    that the return width is fixed for foreign-function callers).  No
  *    exception crosses the ABI.  ann_last_error() returns a thread-local
  *    message describing the last failure of the calling thread.
  *  - On error the index passed in is unchanged and output buffers hold

@@ -37,7 +37,7 @@ namespace ann {
 namespace {
 
 constexpr int PQ_K = 256;        // codewords per subspace
-constexpr int ADC_THREADS = 256;
+constexpr int ADC_THREADS = 1024;  // one workgroup per query: 16 waves, two workgroups per CU by LDS
 constexpr int ADC_BUF = 2048;    // candidate keys buffered before a merge
 constexpr int ADC_SORT = 4096;   // merge sort width (buffer + kept keys, padded)
 constexpr int ADC_KMAX = 1024;
@@ -86,9 +86,7 @@ __global__ void k_ivf_place(const uint8_t* codes_v, const uint8_t* centres, cons
     beta_l[pos] = rr + 2.f * cr;
 }
 
-// key of a candidate: non-negative float distance bits, then the vector id
-__device__ inline uint64_t adc_key(float dist, uint32_t id) { return make_key(f_bits(fmaxf(dist, 0.f)), id); }
-
+// key of a candidate: its non-negative float distance bits, then the vector id
 // sort the first `cnt` keys of buf ascending (bitonic over ADC_SORT entries,
 // the tail padded with empty keys)
 __device__ inline void adc_sort(uint64_t* buf, int cnt) {
@@ -209,12 +207,11 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
         __syncthreads();
     };
 
-    const int64_t per_round = int64_t(ADC_THREADS) * 4;  // a round adds at most ADC_BUF / 2 keys
-    for (int64_t g0 = 0; g0 < total; g0 += per_round) {
+    // a round measures one candidate per thread and adds at most ADC_BUF / 2 keys
+    for (int64_t g0 = 0; g0 < total; g0 += ADC_THREADS) {
         const uint64_t th = *thresh;
-        for (int u = 0; u < 4; ++u) {
-            const int64_t g = g0 + u * ADC_THREADS + t;
-            if (g >= total) break;
+        const int64_t g = g0 + t;
+        if (g < total) {
             // list of candidate g: the last w with pre[w] <= g
             int lo = 0, hi = W - 1;
             while (lo < hi) {
@@ -241,11 +238,14 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc += table[(4 * h + j) * PQ_K + ((w4[h] >> (8 * j)) & 255u)];
             }
-            const float dist = ldist[lo] + beta[pos] - 2.f * acc;
-            const uint64_t key = adc_key(dist, ids[pos]);
-            if (key < th) {
-                const int slot = atomicAdd(&sc[0], 1);
-                buf[slot] = key;
+            const uint32_t db = f_bits(fmaxf(ldist[lo] + beta[pos] - 2.f * acc, 0.f));
+            // the id is read only for a candidate that can enter
+            if (db <= key_dist(th)) {
+                const uint64_t key = make_key(db, ids[pos]);
+                if (key < th) {
+                    const int slot = atomicAdd(&sc[0], 1);
+                    buf[slot] = key;
+                }
             }
         }
         __syncthreads();

@@ -1403,12 +1403,12 @@ struct Plan {
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 constexpr int kLdsGranule = 2560;  // LDS allocation granule of a workgroup (160 KB / 64)
 
-// Global slots for multi-sequence state that outgrows LDS.  Up to T = 2048
-// few queries need one and 256 slots serve them; above it most queries move,
-// so there is a slot for every workgroup that can be resident.  At most
-// 512 MiB of slots.  A workspace smaller than the full size gets fewer slots
-// (at least one).
-constexpr int kSmallBudgetSlots = 256;
+// Global slots for multi-sequence state that outgrows LDS: one for every
+// workgroup that can be resident, so a query never finds them all taken
+// (such a query is redone by the second kernel, at many times the cost: on
+// an index whose queries expand tens to hundreds of bridges most queries
+// move, at any budget).  At most 512 MiB of slots.  A workspace smaller
+// than the full size gets fewer slots (at least one).
 constexpr size_t kMaxSlotBytes = size_t(512) << 20;
 
 static int make_plan(const SearchLaunch& s, Plan& pl) {
@@ -1516,7 +1516,7 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     pl.gcap = std::min<int64_t>(int64_t(idx->K) * idx->K, 8192);
     pl.slot_bytes = size_t(mseq_slot_bytes(int(pl.gcap), idx->K, idx->P));
     const int64_t resident = int64_t(cus) * std::max(1, std::min(32, lds_cu / std::max(1, pl.lds1)));
-    int64_t slots = s.Tmax > 2048 ? resident : kSmallBudgetSlots;
+    int64_t slots = resident;
     slots = std::min<int64_t>(slots, int64_t(kMaxSlotBytes / pl.slot_bytes));
     pl.max_slots = int(std::max<int64_t>(1, std::min<int64_t>(slots, s.nq)));
     return ANN_OK;

@@ -33,8 +33,8 @@ class Ivf:
 
     @classmethod
     def build(cls, data: np.ndarray, lists: int, pq_m: int, pq_iters: int = 4, assign_budget: int = 256,
-              seed: int = 0, graph_k: int = 16, P: int = 2, K: int = 32, kmeans_iters: int = 4, bridge_t: int = 1,
-              bridge_b: int = 5, centre_seed: int = 0) -> "Ivf":
+              seed: int = 0, graph_k: int = 16, P: int = 2, K: int = 16, kmeans_iters: int = 4, bridge_t: int = 1,
+              bridge_b: int = 0, centre_seed: int = 0) -> "Ivf":
         data = np.ascontiguousarray(data, dtype=np.uint8)
         n, d = data.shape
         bp = _abi.BuildParams(C.sizeof(_abi.BuildParams), graph_k, P, K, kmeans_iters, bridge_t, bridge_b, 0,
