@@ -553,12 +553,14 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
             hit = ids == gt1[:, None]
             rec = {f"R@{t}": round(float(hit[:, :t].any(1).mean()), 4) for t in (1, 10, 100)}
             adc_ms = total_ms - lists_ms
-            adc_bytes = float(cand.sum()) * (m + 8)
+            adc_bytes = float(cand.sum()) * (m + 4)   # code + beta per candidate
             row = {"m": m, "L": L, "lists_visited": W, "centre_budget": Tc,
                    "candidates_per_query": round(float(cand.mean()), 1), **rec,
                    "batch_ms": round(total_ms, 3), "list_search_ms": round(lists_ms, 3), "adc_ms": round(adc_ms, 3),
                    "qps": round(nq / (total_ms * 1e-3), 1), "us_per_query": round(total_ms * 1e3 / nq, 3),
-                   "adc_GBps": round(adc_bytes / max(adc_ms, 1e-6) / 1e6, 1), "build_s": round(build_s, 1)}
+                   "adc_GBps": round(adc_bytes / max(adc_ms, 1e-6) / 1e6, 1),
+                   "adc_frac": round(adc_bytes / max(adc_ms, 1e-6) / 1e6 / HBM_PEAK_GBS, 4),
+                   "build_s": round(build_s, 1)}
             log(f"[adc] m={m} L={L}: lists {W}, {row['candidates_per_query']:.0f} candidates, {rec}, "
                 f"{total_ms:.2f} ms per {nq} queries (lists {lists_ms:.2f}), {row['qps']:.0f} QPS")
             out.append(row)

@@ -1456,11 +1456,15 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.nseeds = s.graph_only ? s.n_seeds : 0;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates); buckets for a final load of about 0.8 (its lookups
-    // sit on the look-ahead's critical path: at 0.92 the 1M x 128 search took
-    // 15% longer).  The distance cache (cleared when 5/8 full) gets at least
-    // 56 buckets and grows into the slack of the last LDS granule (below).
-    a.hash_buckets = uint32_t(std::max<int64_t>(4, (int64_t(s.Tmax) + WAVE) * 5 / 4 / 4 + 1));
+    // than it evaluates).  Up to T = 2048 buckets for a final load of about
+    // 0.8 (its lookups sit on the look-ahead's critical path: at 0.92 the
+    // 1M x 128 search took 15% longer); above it the table is most of a
+    // query's LDS and residency matters more: load 0.9 (10M x 128 uneven
+    // batch: 31.6 -> 28.1 ms; 0.95 was slower again).  The distance cache
+    // (cleared when 5/8 full) gets at least 56 buckets and grows into the
+    // slack of the last LDS granule (below).
+    const int64_t visit_ids = int64_t(s.Tmax) + WAVE;
+    a.hash_buckets = uint32_t(std::max<int64_t>(4, (s.Tmax > 2048 ? visit_ids * 10 / 9 : visit_ids * 5 / 4) / 4 + 1));
     a.dc_buckets = 56;
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
@@ -1473,12 +1477,15 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // The state is only fast in LDS: a query that outgrows it continues at L2
     // latency, one lane at a time.  With four lists of at most 64 codewords
     // a query at T <= 2048 expands about one bridge and 8 elements per side
-    // suffice; with three lists or K >= 100 (fewer, larger sides, and tens
-    // to hundreds of bridges expanded per query) the state gets 256, or 512
-    // when the whole batch is still resident at that size (below), and the
-    // short bridge lists are fetched ahead at every budget.
+    // suffice; above it 64 (a larger state costs a resident query per CU,
+    // which the 1M x 128 search at T = 3072 loses more to than it gains from
+    // fewer moves: 43 -> 33 ms at 64); with three lists or K >= 100 (fewer,
+    // larger sides, and tens to hundreds of bridges expanded per query) the
+    // state gets 256, or 512 when the whole batch is still resident at that
+    // size (below), and the short bridge lists are fetched ahead at every
+    // budget.
     const bool few_bridges = idx->P >= 4 && idx->K <= 64;
-    a.ms_cap = int(std::min<int64_t>(side, s.Tmax <= 2048 && few_bridges ? 8 : 256));
+    a.ms_cap = int(std::min<int64_t>(side, few_bridges ? (s.Tmax <= 2048 ? 8 : 64) : 256));
     a.prefetch = (s.Tmax > 2048 || !few_bridges) ? 1 : 0;
     a.gen_batch = s.Tmax <= 2048 ? 16 : GEN_BATCH;
 
