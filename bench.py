@@ -658,7 +658,10 @@ def main():
         gt, _ = knn_device(xd, qd, 1)
         torch.cuda.synchronize()
         del xd
-        print(json.dumps({"graph_d_adc": graph_d_adc_leg(X, Q, gt.cpu().numpy()[:, 0], torch)}), flush=True)
+        line = {"graph_d_adc": graph_d_adc_leg(X, Q, gt.cpu().numpy()[:, 0], torch)}
+        if args.copy_probe:
+            copy_probe(torch)
+        print(json.dumps(line), flush=True)
         return
     t0 = time.time()
     X = synth.base_vectors(w)

@@ -64,7 +64,11 @@ constexpr int KM_CHUNK_BYTES = 32768;  // codewords staged in LDS per pass
 constexpr int KM_SLICE = 64;           // dimensions summed by one workgroup
 constexpr int KM_POINTS = 2048;        // points per accumulation workgroup
 
-template <bool FLOAT>
+// MAXDS > 0: the point's subvector (ds <= MAXDS dims, a multiple of 4 for
+// u8) is held in registers for the whole codeword loop; MAXDS = 0 reads it
+// again for every codeword (any ds).  The arithmetic and its order are the
+// same either way.
+template <bool FLOAT, int MAXDS>
 __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int K,
                                                               const void* cb_p, int kc, int32_t* assign) {
     extern __shared__ __align__(16) uint8_t lds[];
@@ -73,6 +77,26 @@ __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, 
     uint32_t* cnorm = reinterpret_cast<uint32_t*>(lds + ((kc * ds * esz + 15) & ~15));  // u8: |c|^2
     const int64_t i = int64_t(blockIdx.x) * KM_THREADS + threadIdx.x;
     const bool live = i < n;
+    constexpr int RW = MAXDS > 0 ? (FLOAT ? MAXDS : MAXDS / 4) : 1;  // register words of the subvector
+    float xf[FLOAT ? RW : 1];
+    uint32_t xu[FLOAT ? 1 : RW];
+    if constexpr (MAXDS > 0) {
+        if (live) {
+            if constexpr (FLOAT) {
+                const float* x = reinterpret_cast<const float*>(X) + i * d + int64_t(p) * ds;
+#pragma unroll
+                for (int e = 0; e < RW; ++e) xf[e] = e < ds ? x[e] : 0.f;
+            } else {
+                const uint8_t* x = X + i * d + int64_t(p) * ds;
+#pragma unroll
+                for (int w = 0; w < RW; ++w) {
+                    uint32_t v = 0;
+                    if (4 * w < ds) __builtin_memcpy(&v, x + 4 * w, 4);
+                    xu[w] = v;
+                }
+            }
+        }
+    }
     int best = 0;
     uint32_t bd = 0;
     for (int j0 = 0; j0 < K; j0 += kc) {
@@ -97,27 +121,48 @@ __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, 
             const int j = j0 + jj;
             uint32_t dist;
             if constexpr (!FLOAT) {
-                const uint8_t* x = X + i * d + int64_t(p) * ds;
                 const uint8_t* c = c_l + jj * ds;
                 uint32_t dot = 0;
-                int e = 0;
-                if ((ds & 3) == 0) {
-                    for (; e < ds; e += 4) {
-                        uint32_t xw, cw;
-                        __builtin_memcpy(&xw, x + e, 4);
-                        __builtin_memcpy(&cw, c + e, 4);
-                        dot = __builtin_amdgcn_udot4(xw, cw, dot, false);
+                if constexpr (MAXDS > 0) {
+#pragma unroll
+                    for (int w = 0; w < RW; ++w) {
+                        if (4 * w < ds) {
+                            uint32_t cw;
+                            __builtin_memcpy(&cw, c + 4 * w, 4);
+                            dot = __builtin_amdgcn_udot4(xu[w], cw, dot, false);
+                        }
                     }
+                } else {
+                    const uint8_t* x = X + i * d + int64_t(p) * ds;
+                    int e = 0;
+                    if ((ds & 3) == 0) {
+                        for (; e < ds; e += 4) {
+                            uint32_t xw, cw;
+                            __builtin_memcpy(&xw, x + e, 4);
+                            __builtin_memcpy(&cw, c + e, 4);
+                            dot = __builtin_amdgcn_udot4(xw, cw, dot, false);
+                        }
+                    }
+                    for (; e < ds; ++e) dot += uint32_t(x[e]) * c[e];
                 }
-                for (; e < ds; ++e) dot += uint32_t(x[e]) * c[e];
                 dist = cnorm[jj] - 2u * dot + 0x80000000u;  // order-preserving bias (value may be negative)
             } else {
-                const float* x = reinterpret_cast<const float*>(X) + i * d + int64_t(p) * ds;
                 const float* c = reinterpret_cast<const float*>(c_l) + jj * ds;
                 float acc = 0.f;
-                for (int e = 0; e < ds; ++e) {
-                    const float t = x[e] - c[e];
-                    acc = fmaf(t, t, acc);
+                if constexpr (MAXDS > 0) {
+#pragma unroll
+                    for (int e = 0; e < RW; ++e) {
+                        if (e < ds) {
+                            const float t = xf[e] - c[e];
+                            acc = fmaf(t, t, acc);
+                        }
+                    }
+                } else {
+                    const float* x = reinterpret_cast<const float*>(X) + i * d + int64_t(p) * ds;
+                    for (int e = 0; e < ds; ++e) {
+                        const float t = x[e] - c[e];
+                        acc = fmaf(t, t, acc);
+                    }
                 }
                 dist = __float_as_uint(acc);
             }
@@ -128,6 +173,23 @@ __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, 
         }
     }
     if (live) assign[i] = best;
+}
+
+// one assignment launch for subspace p, the register form when ds allows
+template <bool FLOAT>
+void launch_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int K, const void* cb_p, int kc,
+                          int lds, int32_t* assign, hipStream_t s) {
+    const dim3 grid(static_cast<unsigned>(ceil_div(n, KM_THREADS)));
+    const bool words = FLOAT || (ds & 3) == 0;
+    if (words && ds <= 16)
+        hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 16>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
+                           assign);
+    else if (words && ds <= 64)
+        hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 64>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
+                           assign);
+    else
+        hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 0>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
+                           assign);
 }
 
 template <bool FLOAT>
@@ -376,7 +438,6 @@ int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
         return set_error(ANN_EUNSUPPORTED, "codebooks too large for the k-means kernels");
     int32_t* assign = nullptr;
     ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&assign), size_t(idx->n) * 4, s));
-    const int64_t grid = ceil_div(idx->n, KM_THREADS);
     const dim3 agrid(unsigned(ceil_div(idx->n, KM_POINTS)), unsigned(slices));
     for (int it = 0; it < iters; ++it) {
         ANN_HIP_CHECK(hipMemsetAsync(sums, 0, size_t(PKd) * 8, s));
@@ -386,13 +447,11 @@ int build_codebooks(ann_index* idx, int iters, int fx_log2, hipStream_t s) {
             uint64_t* sums_p = sums + int64_t(p) * K * ds;
             uint32_t* counts_p = counts + p * K;
             if (f) {
-                hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s,
-                                   idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, assign);
+                launch_kmeans_assign<true>(idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, lds_assign, assign, s);
                 hipLaunchKernelGGL(k_kmeans_accum<true>, agrid, dim3(KM_THREADS), lds_accum, s, idx->X, idx->n,
                                    idx->d, ds, p, K, assign, fx, sums_p, counts_p);
             } else {
-                hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s,
-                                   idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, assign);
+                launch_kmeans_assign<false>(idx->X, idx->n, idx->d, ds, p, K, cb_p, kc, lds_assign, assign, s);
                 hipLaunchKernelGGL(k_kmeans_accum<false>, agrid, dim3(KM_THREADS), lds_accum, s, idx->X, idx->n,
                                    idx->d, ds, p, K, assign, fx, sums_p, counts_p);
             }
@@ -418,13 +477,10 @@ int kmeans_assign_subspace(const uint8_t* X, int64_t n, int d, bool f32, int ds,
     const int esz = f32 ? 4 : 1;
     const int kc = std::max(1, std::min(K, KM_CHUNK_BYTES / (ds * esz)));
     const int lds_assign = ((kc * ds * esz + 15) & ~15) + kc * 4;
-    const int64_t grid = ceil_div(n, KM_THREADS);
     if (f32)
-        hipLaunchKernelGGL(k_kmeans_assign<true>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s, X, n, d, ds,
-                           p, K, cb_p, kc, assign);
+        launch_kmeans_assign<true>(X, n, d, ds, p, K, cb_p, kc, lds_assign, assign, s);
     else
-        hipLaunchKernelGGL(k_kmeans_assign<false>, dim3(unsigned(grid)), dim3(KM_THREADS), lds_assign, s, X, n, d, ds,
-                           p, K, cb_p, kc, assign);
+        launch_kmeans_assign<false>(X, n, d, ds, p, K, cb_p, kc, lds_assign, assign, s);
     ANN_HIP_CHECK(hipGetLastError());
     return ANN_OK;
 }
