@@ -449,37 +449,10 @@ __device__ inline int write_lane(int v, int x, int l) {
 }
 
 // Offer the keys of the lanes with `isnew` (distinct, none present) to the
-// sorted array v[0..n) of capacity cap: each one goes to its rank and the
-// tail moves up one place; at capacity the largest key falls off.  Same
-// result as a bounded set that evicts its largest key when full.
-template <int KPL>
-__device__ inline void reg_insert(uint64_t (&v)[KPL], int& n, int cap, uint64_t x, bool isnew, int lane) {
-    uint64_t nm = __ballot(isnew);
-    while (nm) {
-        const int j = __builtin_ctzll(nm);
-        nm &= nm - 1;
-        const uint64_t xj = readlane64(x, j);
-        if (n == cap && xj > reg_get<KPL>(v, n - 1)) continue;
-        int pos = 0;
-#pragma unroll
-        for (int u = 0; u < KPL; ++u) pos += __popcll(__ballot(lane + u * WAVE < n && v[u] < xj));
-        uint64_t carry = KEY_EMPTY;  // lane 63 of the previous register
-#pragma unroll
-        for (int u = 0; u < KPL; ++u) {
-            const uint64_t next_carry = readlane64(v[u], WAVE - 1);
-            const uint64_t sh = wave_shr1(v[u], carry);
-            const int e = lane + u * WAVE;
-            v[u] = e < pos ? v[u] : (e == pos ? xj : sh);
-            carry = next_carry;
-        }
-        if (n < cap) ++n;
-    }
-}
-
-// The same offer for one key per lane (cap <= 64), all new keys at once:
-// the result is the smallest min(cap, n + m) of the old and new keys,
-// sorted, which is what offering them one at a time to a bounded set that
-// evicts its largest key leaves.  Each key's place is its rank among old and
+// sorted array v[0..n) of capacity cap <= 64 (one key per lane), all new keys
+// at once: the result is the smallest min(cap, n + m) of the old and new
+// keys, sorted, which is what offering them one at a time to a bounded set
+// that evicts its largest key leaves.  Each key's place is its rank among old and
 // new keys, counted in one pass over the new keys; the keys are written to
 // their places in LDS (buf: 64 keys for this wavefront) and read back.
 __device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool isnew, int lane, uint64_t* buf) {
@@ -507,6 +480,53 @@ __device__ inline void reg_merge1(uint64_t& v, int& n, int cap, uint64_t x, bool
     lds_wave_order();
     const int total = min(cap, n + m);
     v = lane < total ? buf[lane] : KEY_EMPTY;
+    n = total;
+    lds_wave_order();
+}
+
+// reg_merge1 for a sorted array of KPL keys per lane (element e in lane
+// e % 64, register e / 64; elements at or past n hold KEY_EMPTY): each key's
+// place is its rank among old and new keys, counted in one pass over the new
+// keys; buf holds KPL * 64 keys.  A new key costs KPL compares and ballots
+// instead of a shift of the whole array.
+template <int KPL>
+__device__ inline void reg_mergeN(uint64_t (&v)[KPL], int& n, int cap, uint64_t x, bool isnew, int lane,
+                                  uint64_t* buf) {
+    uint64_t nm = __ballot(isnew);
+    const int m = __popcll(nm);
+    int above[KPL];
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) above[u] = 0;
+    int new_below = 0, old_below = 0;
+    while (nm) {
+        const int j = __builtin_ctzll(nm);
+        nm &= nm - 1;
+        const uint64_t xj = readlane64(x, j);
+        int ob = KPL * WAVE;  // old elements below x_j: all but those above it (keys are distinct)
+#pragma unroll
+        for (int u = 0; u < KPL; ++u) {
+            const bool lt = xj < v[u];
+            above[u] += lt ? 1 : 0;
+            ob -= __popcll(__ballot(lt));
+        }
+        new_below += xj < x ? 1 : 0;
+        old_below = write_lane(old_below, ob, j);
+    }
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+        const int e = lane + u * WAVE;
+        const int po = e + above[u];
+        if (e < n && po < cap) buf[po] = v[u];
+    }
+    const int pn = old_below + new_below;
+    if (isnew && pn < cap) buf[pn] = x;
+    lds_wave_order();
+    const int total = min(cap, n + m);
+#pragma unroll
+    for (int u = 0; u < KPL; ++u) {
+        const int e = lane + u * WAVE;
+        v[u] = e < total ? buf[e] : KEY_EMPTY;
+    }
     n = total;
     lds_wave_order();
 }
@@ -724,7 +744,7 @@ k_search(SearchArgs a) {
     uint32_t* gid = reinterpret_cast<uint32_t*>(lds + a.o_gid);
     uint32_t* gd = reinterpret_cast<uint32_t*>(lds + a.o_gd);
     int* sc = reinterpret_cast<int*>(lds + a.o_sc);
-    uint64_t* mrg = reinterpret_cast<uint64_t*>(lds + a.o_mrg);  // merge buffer, 64 keys
+    uint64_t* mrg = reinterpret_cast<uint64_t*>(lds + a.o_mrg);  // merge buffer, 64 keys a result register
 
 
     const int lane = lane_id();
@@ -845,7 +865,7 @@ k_search(SearchArgs a) {
                 if constexpr (KPL == 1)
                     reg_merge1(Rv[0], rn, rcap, key, ra, lane, mrg);
                 else
-                    reg_insert<KPL>(Rv, rn, rcap, key, ra, lane);
+                    reg_mergeN<KPL>(Rv, rn, rcap, key, ra, lane, mrg);
             }
             const uint64_t qworst = qn < a.L ? KEY_EMPTY : readlane64(Qv[0], qn - 1);
             const bool qa = ev && key < qworst;
@@ -1345,7 +1365,7 @@ int layout(SearchArgs& a, int qbytes, int PK, int rcap, bool with_heap, bool bf1
     a.o_gid = take(bf16 ? std::max(WAVE * 4, rcap * 8) : (lpr > 1 ? WAVE * 4 : 8), 8);
     a.o_gd = take(lpr > 1 ? WAVE * 4 : 8, 8);
     a.o_sc = take(16 * 4, 8);
-    a.o_mrg = take(WAVE * 8, 8);
+    a.o_mrg = take(align_up(std::max(rcap, WAVE), WAVE) * 8, 8);
     return align_up(off, 16);
 }
 
