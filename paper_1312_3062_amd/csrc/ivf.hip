@@ -42,6 +42,7 @@ constexpr int ADC_BUF = 2048;    // candidate keys buffered before a merge
 constexpr int ADC_SORT = 4096;   // merge sort width (buffer + kept keys, padded)
 constexpr int ADC_KMAX = 1024;
 constexpr int ADC_WMAX = 1024;   // lists per query
+constexpr int ADC_RMAX = 256;    // rounds whose first candidate's list is found once, up front
 
 __global__ void k_ivf_residual(const uint8_t* X, int64_t n, int d, const uint8_t* centres, const int32_t* assign,
                                float* resid) {
@@ -123,7 +124,8 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
     uint32_t* pre = reinterpret_cast<uint32_t*>(sc + 4);               // W + 1 prefix of list lengths
     uint32_t* lstart = pre + ADC_WMAX + 4;                             // W list starts
     float* ldist = reinterpret_cast<float*>(lstart + ADC_WMAX);        // W centre distances
-    float* qf = ldist + ADC_WMAX;                                      // d
+    uint32_t* rlo = reinterpret_cast<uint32_t*>(ldist + ADC_WMAX);     // ADC_RMAX: list of a round's first candidate
+    float* qf = reinterpret_cast<float*>(rlo + ADC_RMAX);              // d
     const int64_t qi = blockIdx.x;
     const int t = threadIdx.x;
 
@@ -153,10 +155,43 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
         for (int q = 0; q < ds; ++q) acc = fmaf(qf[j * ds + q], cw[q], acc);
         table[e] = acc;
     }
-    if (t == 0)
-        for (int w = 0; w < W; ++w) pre[w + 1] += pre[w];  // at most 1024 lists: one lane
-    __syncthreads();
+    // prefix sums of the list lengths (W <= 1024: one per thread): scans
+    // within each wavefront, then the wavefront totals (staged in rlo, which
+    // is filled only afterwards)
+    {
+        static_assert(ADC_WMAX <= ADC_THREADS && ADC_THREADS / WAVE <= ADC_RMAX, "one list per thread");
+        const int lane = t % WAVE, wv = t / WAVE;
+        uint32_t v = t < W ? pre[t + 1] : 0u;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(v, o, WAVE);
+            if (lane >= o) v += y;
+        }
+        if (lane == WAVE - 1) rlo[wv] = v;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int i = 0; i < wv; ++i) before += rlo[i];
+        if (t < W) pre[t + 1] = v + before;
+        __syncthreads();
+    }
     const int64_t total = min(int64_t(pre[W]), int64_t(L));
+    // list of candidate g: the last w in [lo, hi] with pre[w] <= g (pre[lo] <= g)
+    auto list_of = [&](int64_t g, int lo, int hi) {
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (int64_t(pre[mid]) <= g)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return lo;
+    };
+    // the lists of the rounds' first candidates bound every search to the
+    // few lists a round spans
+    const int64_t rounds = (total + ADC_THREADS - 1) / ADC_THREADS;
+    const int known = int(min(rounds, int64_t(ADC_RMAX)));
+    for (int r = t; r < known; r += ADC_THREADS) rlo[r] = uint32_t(list_of(int64_t(r) * ADC_THREADS, 0, W - 1));
+    __syncthreads();
 
     // merge the buffered keys with the kept ones and keep the best k
     auto merge = [&]() {
@@ -208,19 +243,11 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
     };
 
     // a round measures one candidate per thread and adds at most ADC_BUF / 2 keys
-    for (int64_t g0 = 0; g0 < total; g0 += ADC_THREADS) {
+    for (int64_t g0 = 0, r = 0; g0 < total; g0 += ADC_THREADS, ++r) {
         const uint64_t th = *thresh;
         const int64_t g = g0 + t;
         if (g < total) {
-            // list of candidate g: the last w with pre[w] <= g
-            int lo = 0, hi = W - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (int64_t(pre[mid]) <= g)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
+            const int lo = list_of(g, r < known ? int(rlo[r]) : 0, r + 1 < known ? int(rlo[r + 1]) : W - 1);
             const int64_t pos = int64_t(lstart[lo]) + (g - pre[lo]);
             const uint8_t* cw = codes + pos * M;
             float acc = 0.f;
@@ -273,7 +300,8 @@ __global__ void __launch_bounds__(ADC_THREADS) k_ivf_adc(const uint8_t* Q, int d
 }
 
 int adc_lds_bytes(int M, int d) {
-    return M * PQ_K * 4 + ADC_SORT * 8 + 8 + 16 + (ADC_WMAX + 4) * 4 + ADC_WMAX * 4 + ADC_WMAX * 4 + d * 4;
+    return M * PQ_K * 4 + ADC_SORT * 8 + 8 + 16 + (ADC_WMAX + 4) * 4 + ADC_WMAX * 4 + ADC_WMAX * 4 + ADC_RMAX * 4 +
+           d * 4;
 }
 
 void free_ivf(ann_ivf* v) {
