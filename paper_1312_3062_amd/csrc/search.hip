@@ -1476,15 +1476,15 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     a.nseeds = s.graph_only ? s.n_seeds : 0;
 
     // visited set: at most T + 64 ids (the last adjacency chunk may mark more
-    // than it evaluates).  Up to T = 2048 buckets for a final load of about
-    // 0.8 (its lookups sit on the look-ahead's critical path: at 0.92 the
-    // 1M x 128 search took 15% longer); above it the table is most of a
-    // query's LDS and residency matters more: load 0.9 (10M x 128 uneven
-    // batch: 31.6 -> 28.1 ms; 0.95 was slower again).  The distance cache
-    // (cleared when 5/8 full) gets at least 56 buckets and grows into the
-    // slack of the last LDS granule (below).
+    // than it evaluates), buckets for a final load of about 0.8 (its lookups
+    // sit on the look-ahead's critical path: at 0.92 the 1M x 128 search took
+    // 15% longer), or 0.9 where residency is chosen over latency (below).
+    // The distance cache (cleared when 5/8 full) gets at least 56 buckets and
+    // grows into the slack of the last LDS granule (below).
     const int64_t visit_ids = int64_t(s.Tmax) + WAVE;
-    a.hash_buckets = uint32_t(std::max<int64_t>(4, (s.Tmax > 2048 ? visit_ids * 10 / 9 : visit_ids * 5 / 4) / 4 + 1));
+    auto visited_buckets = [&](bool dense) {
+        return uint32_t(std::max<int64_t>(4, (dense ? visit_ids * 10 / 9 : visit_ids * 5 / 4) / 4 + 1));
+    };
     a.dc_buckets = 56;
     const int max_spec = idx->R > 0 ? std::min(MAX_SPEC, WAVE / idx->R) : 1;
     a.spec = s.lookahead > 0 ? std::min(s.lookahead, max_spec) : max_spec;
@@ -1497,15 +1497,22 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     // The state is only fast in LDS: a query that outgrows it continues at L2
     // latency, one lane at a time.  With four lists of at most 64 codewords
     // a query at T <= 2048 expands about one bridge and 8 elements per side
-    // suffice; above it 64 (a larger state costs a resident query per CU,
-    // which the 1M x 128 search at T = 3072 loses more to than it gains from
-    // fewer moves: 43 -> 33 ms at 64); with three lists or K >= 100 (fewer,
-    // larger sides, and tens to hundreds of bridges expanded per query) the
-    // state gets 256, or 512 when the whole batch is still resident at that
-    // size (below), and the short bridge lists are fetched ahead at every
-    // budget.
+    // suffice.  Between 2048 and 4096 residency wins: 64 elements and the
+    // visited set at load 0.9 keep one more query per CU than 256 at 0.8
+    // (1M x 128 at T = 3072: 43.5 -> 34.0 ms; 10M x 128 uneven batch:
+    // 31.6 -> 28.1 ms).  Above 4096 bridges take over and a state that moves
+    // out of LDS makes its query the slowest of its launch: 256 at 0.8 (a
+    // mixed request stream on the 10M index served 98K queries/s against
+    // 83K), unless the launch has one budget and more queries than fit the
+    // chip at that size, where residency wins again (1M x 128 at T = 8192:
+    // 310 against 398 ms).  With three lists or K >= 100 (fewer, larger
+    // sides, and tens to hundreds of bridges expanded per query) the state
+    // gets 256, or 512 when the whole batch is still resident at that size
+    // (below), and the short bridge lists are fetched ahead at every budget.
     const bool few_bridges = idx->P >= 4 && idx->K <= 64;
-    a.ms_cap = int(std::min<int64_t>(side, few_bridges ? (s.Tmax <= 2048 ? 8 : 64) : 256));
+    const bool mid_budget = s.Tmax > 2048 && s.Tmax <= 4096;
+    a.hash_buckets = visited_buckets(mid_budget);
+    a.ms_cap = int(std::min<int64_t>(side, few_bridges ? (s.Tmax <= 2048 ? 8 : (mid_budget ? 64 : 256)) : 256));
     a.prefetch = (s.Tmax > 2048 || !few_bridges) ? 1 : 0;
     a.gen_batch = s.Tmax <= 2048 ? 16 : GEN_BATCH;
 
@@ -1517,6 +1524,16 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     int cus = 0, lds_cu = 0;
     ANN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, idx->device));
     ANN_HIP_CHECK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, idx->device));
+    if (few_bridges && s.Tmax > 4096 && !s.d_T && a.ms_cap > 64) {
+        // one budget for the whole launch: throughput first when the batch
+        // does not fit the chip at the larger state
+        const int lds_lat = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+        const int64_t granules = ceil_div(lds_lat, kLdsGranule);
+        if (int64_t(cus) * (lds_cu / (granules * kLdsGranule)) < s.nq) {
+            a.ms_cap = int(std::min<int64_t>(side, 64));
+            a.hash_buckets = visited_buckets(true);
+        }
+    }
     if (!few_bridges && a.ms_cap < side) {
         // a batch that fits on the chip either way: the larger state keeps
         // the bridge-heavy queries (the launch's slowest) in LDS
@@ -1549,19 +1566,20 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     return ANN_OK;
 }
 
-// Budget classes.  With per-query budgets a launch serves up to three classes
-// (T <= 512, T <= 2048, larger) by one kernel each, in turn on the stream,
-// each sized (LDS, multi-sequence capacity, slots) by its own largest budget:
-// a few long queries then do not shrink the residency of the many short ones.
+// Budget classes.  With per-query budgets a launch serves up to four classes
+// (T <= 512, T <= 2048, T <= 4096, larger) by one kernel each, in turn on the
+// stream, each sized (LDS, multi-sequence capacity, slots) by its own largest
+// budget: a few long queries then do not shrink the residency of the many
+// short ones, and the longest class keeps the larger state it needs.
 struct ClassPlan {
     Plan pl;
     int t_lo, t_hi;
 };
 
-// at most three classes, held in place (a search launch allocates nothing on
+// at most four classes, held in place (a search launch allocates nothing on
 // the host either)
 struct ClassPlans {
-    ClassPlan c[3];
+    ClassPlan c[4];
     int n = 0;
     ClassPlan* begin() { return c; }
     ClassPlan* end() { return c + n; }
@@ -1571,15 +1589,19 @@ struct ClassPlans {
 
 static int make_class_plans(const SearchLaunch& s, ClassPlans& out) {
     out.n = 0;
-    int ranges[3][2];
+    int ranges[4][2];
     int nr = 0;
     if (!s.d_T || s.Tmax <= 512) {
         ranges[nr][0] = 0;
         ranges[nr++][1] = s.Tmax;
     } else {
+        if (s.Tmax > 4096) {
+            ranges[nr][0] = 4097;
+            ranges[nr++][1] = s.Tmax;
+        }
         if (s.Tmax > 2048) {
             ranges[nr][0] = 2049;
-            ranges[nr++][1] = s.Tmax;
+            ranges[nr++][1] = std::min(s.Tmax, 4096);
         }
         ranges[nr][0] = 513;
         ranges[nr++][1] = std::min(s.Tmax, 2048);

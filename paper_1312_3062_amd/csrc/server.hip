@@ -121,7 +121,11 @@ SearchLaunch launch_of(const ann_server* s, int64_t nq, int k, int T) {
 }
 
 // budget class bound a query of budget T is laid out for inside a launch
-int class_budget(const ann_server* s, int T) { return T <= 512 ? 512 : (T <= 2048 ? 2048 : s->p.max_budget); }
+int class_budget(const ann_server* s, int T) {
+    if (T <= 512) return 512;
+    if (T <= 2048) return 2048;
+    return T <= 4096 ? std::min(4096, s->p.max_budget) : s->p.max_budget;
+}
 
 // device bytes of a micro-batch: query rows, k and budget, results, workspace
 int batch_bytes(const ann_server* s, int64_t nq, int kb, int Tb, int64_t* bytes) {
