@@ -131,7 +131,7 @@ def _check_ranked(gids, gd, oids, od, all_ids, all_d):
 
 
 @pytest.mark.parametrize("W,L,k", [(8, 2_000, 100), (32, 100_000, 100), (1, 50, 10), (64, 5_000, 1024),
-                                   (16, 0, 10)])
+                                   (16, 0, 10), (300, 100_000, 10)])
 def test_search_against_the_oracle(built, W, L, k):
     ivf, parts, Q = built["ivf"], built["parts"], built["Q"]
     qd = torch.from_numpy(Q).cuda()
