@@ -514,6 +514,46 @@ def test_large_budgets_uneven_k_bit_exact():
     assert_search_equal(idx, parts, X, Q, 100, 8192, 64, ks=ks, Ts=Ts)
 
 
+def test_budgets_across_all_four_classes_bit_exact():
+    """Per-query budgets from 64 to 8192 in one launch on an index of four
+    subspaces of 16 codewords: four budget classes (up to 512, 2048, 4096
+    and above), each with its own visited-set load and multi-sequence state,
+    against the oracle (ids, distances and evaluation traces)."""
+    w = synth.scaled(synth.WORKLOADS["hog_like_10m_u8"], 20000, nq=24, d=64, components=64)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 8, 4, 16, 3, 5, 8, 4)
+    parts = idx.export()
+    rng = np.random.default_rng(4096)
+    ks = rng.choice([1, 10, 100], size=len(Q)).astype(np.int32)
+    Ts = np.rint(np.exp(rng.uniform(np.log(64), np.log(8192), size=len(Q)))).astype(np.int32)
+    Ts[:4] = [300, 1500, 3000, 8192]  # every class holds a query
+    gi, gd, st = gpu_search(idx, Q, 100, 8192, 64, ks=ks, Ts=Ts, stats=True)
+    print(f"[four-class] budgets {sorted(Ts.tolist())[:3]}..{Ts.max()}, moved {int(st[:, 10].sum())}, "
+          f"re-run {int(st[:, 9].sum())}", flush=True)
+    assert (st[:, 6] == 0).all()
+    assert_search_equal(idx, parts, X, Q, 100, 8192, 64, ks=ks, Ts=Ts)
+
+
+def test_one_budget_above_4096_for_more_queries_than_fit_sampled():
+    """One budget above 4096 for more queries than the chip holds at the
+    larger multi-sequence state: the launch takes the residency-first state;
+    sampled queries against the oracle."""
+    w = synth.scaled(synth.WORKLOADS["sift_like_1m_u8"], 20000, nq=2000, d=64, components=64)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 8, 4, 16, 3, 5, 8, 4)
+    parts = idx.export()
+    T = 6000
+    gi, gd, st = gpu_search(idx, Q, 10, T, 64, stats=True)
+    assert (st[:, 6] == 0).all()
+    rows = np.random.default_rng(6000).choice(len(Q), 12, replace=False)
+    print(f"[one-budget] {len(Q)} queries at T={T}, moved {int(st[:, 10].sum())}, re-run {int(st[:, 9].sum())}; "
+          f"oracle on rows {rows.tolist()}", flush=True)
+    oi, od = oracle.search(X, parts["codebooks"], parts["graph"], parts["bridge_off"], parts["bridge_ids"], Q[rows],
+                           10, T, 64)
+    np.testing.assert_array_equal(gi[rows], oi)
+    np.testing.assert_array_equal(gd[rows].astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
+
+
 def test_budget_beyond_lds_is_rejected():
     """A visited set for 2^20 evaluations cannot live in one workgroup's LDS:
     the search says so instead of running."""
