@@ -474,7 +474,10 @@ int ann_ivf_export(const ann_ivf* ivf, uint8_t* centres, uint32_t* list_off, uin
  * of them (the scan stops mid-list when they are reached), ranked by the
  * asymmetric distance (fp32).  d_ids nq x k int32, d_dists nq x k float,
  * ascending by (distance, id), padded with -1 / +infinity.  1 <= k <= 1024,
- * 1 <= lists <= 1024.  Asynchronous on `stream`.
+ * 1 <= lists <= 1024.  Asynchronous on `stream`; the lists of the batch
+ * (nq x lists ids and distances) live in a stream-ordered allocation freed
+ * on the same stream.  Errors: ANN_EINVAL, ANN_EUNSUPPORTED (the distance
+ * tables of this d and pq_m exceed a workgroup's LDS), ANN_EDEVICE.
  */
 int ann_ivf_search_device(const ann_ivf* ivf, const void* d_queries, int64_t nq, int32_t k, int32_t lists,
                           int32_t centre_budget, int32_t candidates, int32_t* d_ids, float* d_dists, void* stream);

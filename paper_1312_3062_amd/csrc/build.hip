@@ -3,6 +3,7 @@
 // (Cartesian concatenations of codewords) to reference vectors.
 #include <algorithm>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.hpp"
@@ -23,19 +24,21 @@ static uint64_t splitmix64(uint64_t& state) {
 }
 
 // First K positions of a Fisher-Yates shuffle of [0, n): the initial rows.
+// Only the positions a swap has touched are stored (a vocabulary of millions
+// of rows is drawn in time linear in K).
 void kmeans_init_rows(int64_t n, int K, uint64_t seed, int64_t* rows) {
-    std::vector<std::pair<int64_t, int64_t>> moved;  // (position, value) writes, latest last
+    std::unordered_map<int64_t, int64_t> moved;  // position -> value, where it differs from the position
+    moved.reserve(size_t(2) * size_t(K));
     auto value_at = [&](int64_t i) {
-        for (auto it = moved.rbegin(); it != moved.rend(); ++it)
-            if (it->first == i) return it->second;
-        return i;
+        const auto it = moved.find(i);
+        return it == moved.end() ? i : it->second;
     };
     uint64_t st = seed;
     for (int i = 0; i < K; ++i) {
         const int64_t j = i + int64_t(splitmix64(st) % uint64_t(n - i));
         const int64_t vi = value_at(i), vj = value_at(j);
-        moved.emplace_back(i, vj);
-        moved.emplace_back(j, vi);
+        moved[i] = vj;
+        moved[j] = vi;
         rows[i] = vj;
     }
 }
