@@ -69,7 +69,7 @@ constexpr int KM_POINTS = 2048;        // points per accumulation workgroup
 
 // MAXDS > 0: the point's subvector (ds <= MAXDS dims, a multiple of 4 for
 // u8) is held in registers for the whole codeword loop; MAXDS = 0 reads it
-// again for every codeword (any ds).  The arithmetic and its order are the
+// again for every codeword (any ds; used above 128 dims).  The arithmetic and its order are the
 // same either way.
 template <bool FLOAT, int MAXDS>
 __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int K,
@@ -189,6 +189,9 @@ void launch_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int
                            assign);
     else if (words && ds <= 64)
         hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 64>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
+                           assign);
+    else if (words && ds <= 128)
+        hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 128>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
                            assign);
     else
         hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 0>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
