@@ -302,7 +302,10 @@ __global__ void __launch_bounds__(256) k_knn_mfma(const uint8_t* X, const uint32
             }
             const int jj = cb * 16 + col;
             const int64_t j = j0 + jj;
-            const int ncn = -cn_l[cur][jj];  // past the tile's end: too small to pass
+            int ncn = -cn_l[cur][jj];  // past the tile's end: too small to pass
+            // opaque to the compiler, so that 2 u.v - |v|^2 is one shift-add
+            // per value rather than a shift and a subtraction of |v|^2
+            asm volatile("" : "+v"(ncn));
             bool any = false;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
