@@ -85,6 +85,12 @@ struct SearchArgs {
     int graph_only;          // neighborhood-graph search without bridges
     const uint32_t* seeds;   // its seed ids, measured first
     int nseeds;
+    // budgets whose visited set does not fit LDS: a bitmap over the n vectors
+    // per workgroup in global memory (workgroup b owns bitmap b; null: the
+    // LDS set)
+    uint32_t* gvis;
+    int64_t gvis_words;      // 32-bit words of a bitmap
+    int gvis_slots;          // bitmaps (the grids are capped to it)
     // LDS layout (byte offsets)
     int o_mrg;  // merge buffer of the register queues
     int o_q, o_sv, o_perm, o_ms, o_rk, o_ro, o_rl, o_sk, o_pid, o_pd, o_hash, o_dck, o_dcv, o_scr, o_gid, o_gd,
@@ -368,6 +374,13 @@ __device__ inline int set_insert(uint32_t* T, uint32_t nbk, uint32_t id, bool& f
     }
     fresh = false;
     return -1;
+}
+
+// Atomic OR on a word known to be in global memory (a generic pointer would
+// make the compiler test at run time whether it addresses LDS).
+typedef __attribute__((address_space(1))) uint32_t global_u32;
+__device__ inline uint32_t global_or(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_or((global_u32*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The distance cache's values carry a visited flag in their top bit (u8
@@ -738,6 +751,9 @@ k_search(SearchArgs a) {
     uint32_t* pre_id = reinterpret_cast<uint32_t*>(lds + a.o_pid);  // prefetched bridge lists, 8 per entry
     uint32_t* pre_d = reinterpret_cast<uint32_t*>(lds + a.o_pd);    // and their distances
     uint32_t* H = reinterpret_cast<uint32_t*>(lds + a.o_hash);
+    // budgets beyond LDS: this workgroup's visited bitmap in global memory
+    // (its address is formed where used, never kept live across the search)
+    const bool gvis = a.gvis != nullptr;
     uint32_t* DK = reinterpret_cast<uint32_t*>(lds + a.o_dck);
     uint32_t* DV = reinterpret_cast<uint32_t*>(lds + a.o_dcv);
     uint64_t* scratch = reinterpret_cast<uint64_t*>(lds + a.o_scr);
@@ -793,6 +809,10 @@ k_search(SearchArgs a) {
         const bool graph_only = a.graph_only != 0;  // neighborhood-graph search, no bridges
         if (!graph_only) compute_tables<FLOAT>(qv, a.cb, P, K, a.ds, H, sv, perm, lane);
         for (int i = lane; i < HW; i += WAVE) H[i] = ID_EMPTY;
+        if (gvis) {
+            global_u32* gv = (global_u32*)(a.gvis + int64_t(blockIdx.x) * a.gvis_words);
+            for (int64_t i = lane; i < a.gvis_words; i += WAVE) gv[i] = 0u;
+        }
         __syncthreads();
         int slot = -1;  // global slot the enumeration moved to (main kernel)
         // where the enumeration state lives: LDS, or a global slot (the re-run
@@ -872,6 +892,25 @@ k_search(SearchArgs a) {
             if (__ballot(qa)) reg_merge1(Qv[0], qn, a.L, key, qa, lane, mrg);
         };
 
+        // the visited set: the LDS table, or the global bitmap (atomics at L2:
+        // a lane reads what the wave's other lanes set)
+        auto vis_insert = [&](uint32_t vid, bool& fresh) -> bool {
+            if (gvis) {
+                const uint32_t bit = 1u << (vid & 31u);
+                uint32_t* w = a.gvis + int64_t(blockIdx.x) * a.gvis_words + (vid >> 5);
+                fresh = (global_or(w, bit) & bit) == 0u;
+                return true;
+            }
+            return set_insert(H, a.hash_buckets, vid, fresh) >= 0;
+        };
+        auto vis_has = [&](uint32_t vid) -> bool {
+            if (gvis) {
+                uint32_t* w = a.gvis + int64_t(blockIdx.x) * a.gvis_words + (vid >> 5);
+                return (global_or(w, 0u) >> (vid & 31u)) & 1u;
+            }
+            return set_has(H, a.hash_buckets, vid);
+        };
+
         // a bridge's list entry: visited unless the cache flags it or H holds
         // it, marked visited either way; `cached` gets the distance the cache
         // holds for it, or ID_EMPTY
@@ -885,7 +924,7 @@ k_search(SearchArgs a) {
                 return (old & VISITED_FLAG) == 0u;
             }
             bool fresh = false;
-            if (set_insert(H, a.hash_buckets, vid, fresh) < 0) full = true;
+            if (!vis_insert(vid, fresh)) full = true;
             return fresh;
         };
 
@@ -972,7 +1011,7 @@ k_search(SearchArgs a) {
                         if (with_dist) {
                             bool need = false;
                             uint32_t d = 0;
-                            if (pid != ID_EMPTY && !set_has(H, a.hash_buckets, pid)) {
+                            if (pid != ID_EMPTY && !vis_has(pid)) {
                                 const int ds = set_find(DK, a.dc_buckets, pid);
                                 if (ds >= 0)
                                     d = DV[ds] & DIST_BITS;
@@ -1071,7 +1110,7 @@ k_search(SearchArgs a) {
                             uint32_t vid = ID_EMPTY;
                             if (i < DW && (DV[i] & VISITED_FLAG)) vid = DK[i];
                             bool fresh = false;
-                            if (vid != ID_EMPTY && set_insert(H, a.hash_buckets, vid, fresh) < 0) full = true;
+                            if (vid != ID_EMPTY && !vis_insert(vid, fresh)) full = true;
                         }
                         for (int i = lane; i < DW; i += WAVE) DK[i] = ID_EMPTY;
                         dc_fill = 0;
@@ -1080,7 +1119,7 @@ k_search(SearchArgs a) {
                     ac_id = nid;
                     bool need = false, known = false;
                     int slot = 0;
-                    if (ac_id != ID_EMPTY && !set_has(H, a.hash_buckets, ac_id)) {
+                    if (ac_id != ID_EMPTY && !vis_has(ac_id)) {
                         known = true;
                         slot = set_insert(DK, a.dc_buckets, ac_id, need);
                         if (slot < 0) {
@@ -1386,6 +1425,7 @@ int launch_mode_c(const SearchArgs& a1, const SearchArgs& a2, int lds1, int lds2
         if (g.waves_per_cu > 0) per_cu = std::min(per_cu, g.waves_per_cu);
         grid = std::min<int64_t>(a1.nq, int64_t(per_cu) * g.cus);
     }
+    if (a1.gvis) grid = std::min<int64_t>(grid, a1.gvis_slots);  // workgroup b owns visited bitmap b
     hipLaunchKernelGGL(k1, dim3(unsigned(grid)), dim3(WAVE), lds1, st, a1);
     hipLaunchKernelGGL((k_search<MODE, NC16, KPL, true, COUNT>), dim3(unsigned(grid2)), dim3(WAVE), lds2, st, a2);
     return ANN_OK;
@@ -1418,6 +1458,9 @@ struct Plan {
     int64_t gcap = 0;
     size_t slot_bytes = 0;
     int max_slots = 0;
+    bool gvis = false;       // the visited set is a global bitmap (budget beyond LDS)
+    int64_t gvis_words = 0;  // words of one bitmap
+    int gvis_slots = 0;      // bitmaps wanted (one per workgroup of the grid)
 };
 
 static size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
@@ -1430,6 +1473,10 @@ constexpr int kLdsGranule = 2560;  // LDS allocation granule of a workgroup (160
 // move, at any budget).  At most 512 MiB of slots.  A workspace smaller
 // than the full size gets fewer slots (at least one).
 constexpr size_t kMaxSlotBytes = size_t(512) << 20;
+// Visited bitmaps of budgets beyond LDS: at most 1 GiB of them (the grid of
+// such a class is capped to the bitmaps; each workgroup clears its own per
+// query, n / 8 bytes, against the T rows of at least 100 bytes it gathers).
+constexpr size_t kMaxBitmapBytes = size_t(1) << 30;
 
 static int make_plan(const SearchLaunch& s, Plan& pl) {
     const ann_index* idx = s.idx;
@@ -1552,6 +1599,21 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
         a.dc_buckets = uint32_t(std::min(128, 56 + slack / 32));
         pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
     }
+    int max_lds = 0;
+    ANN_HIP_CHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, idx->device));
+    if (pl.lds1 > max_lds) {
+        // the visited set for this budget does not fit a workgroup's LDS: a
+        // bitmap over the vectors in global memory takes its place (the LDS
+        // table's memory still holds the raw distance tables first)
+        pl.gvis = true;
+        pl.gvis_words = ceil_div(idx->n, 32);
+        a.hash_buckets = 4;
+        a.dc_buckets = 56;
+        pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+        const int slack = int(ceil_div(pl.lds1, kLdsGranule) * kLdsGranule) - pl.lds1;
+        a.dc_buckets = uint32_t(std::min(128, 56 + slack / 32));
+        pl.lds1 = layout(a, qbytes, PK, pl.rcap, true, pl.bf16, lpr);
+    }
     pl.a2 = a;
     pl.lds2 = layout(pl.a2, qbytes, PK, pl.rcap, false, pl.bf16, lpr);
 
@@ -1563,6 +1625,10 @@ static int make_plan(const SearchLaunch& s, Plan& pl) {
     int64_t slots = resident;
     slots = std::min<int64_t>(slots, int64_t(kMaxSlotBytes / pl.slot_bytes));
     pl.max_slots = int(std::max<int64_t>(1, std::min<int64_t>(slots, s.nq)));
+    if (pl.gvis) {
+        const int64_t fit = std::max<int64_t>(1, int64_t(kMaxBitmapBytes / (size_t(pl.gvis_words) * 4)));
+        pl.gvis_slots = int(std::max<int64_t>(1, std::min(std::min<int64_t>(resident, s.nq), fit)));
+    }
     return ANN_OK;
 }
 
@@ -1629,6 +1695,8 @@ static int make_class_plans(const SearchLaunch& s, ClassPlans& out) {
 struct WsLayout {
     int max_slots = 0, bit_words = 0;
     size_t slot_bytes = 0, fixed = 0, total = 0;
+    int gvis_max = 0;        // visited bitmaps (0: every class keeps its set in LDS)
+    size_t gvis_each = 0;    // bytes of one bitmap
 };
 
 static WsLayout ws_layout(const ClassPlans& cl, int64_t nq) {
@@ -1638,16 +1706,25 @@ static WsLayout ws_layout(const ClassPlans& cl, int64_t nq) {
     L.bit_words = int(ceil_div(L.max_slots, 32));
     L.fixed = (256 + round16(size_t(L.bit_words) * 4) + round16(size_t(nq) * 4) + 256 + round16(size_t(nq) * 4) + 63) &
               ~size_t(63);
-    L.total = L.fixed + size_t(L.max_slots) * L.slot_bytes;
+    for (const auto& c : cl)
+        if (c.pl.gvis) {
+            L.gvis_max = std::max(L.gvis_max, c.pl.gvis_slots);
+            L.gvis_each = (size_t(c.pl.gvis_words) * 4 + 255) & ~size_t(255);
+        }
+    L.total = L.fixed + size_t(L.gvis_max) * L.gvis_each + size_t(L.max_slots) * L.slot_bytes;
     return L;
 }
+
+// smallest workspace: one visited bitmap (if any class needs them) and one
+// multi-sequence slot
+static size_t ws_minimum(const WsLayout& L) { return L.fixed + (L.gvis_max > 0 ? L.gvis_each : 0) + L.slot_bytes; }
 
 int search_workspace_bytes(const SearchLaunch& s, int64_t* bytes, bool minimum) {
     ClassPlans cl;
     int rc = make_class_plans(s, cl);
     if (rc) return rc;
     const WsLayout L = ws_layout(cl, s.nq);
-    *bytes = int64_t(minimum ? L.fixed + L.slot_bytes : L.total);
+    *bytes = int64_t(minimum ? ws_minimum(L) : L.total);
     return ANN_OK;
 }
 
@@ -1681,14 +1758,22 @@ int launch_search(const SearchLaunch& s) {
     uint8_t* w = static_cast<uint8_t*>(s.workspace);
     const bool own = w == nullptr;
     int avail = L.max_slots;
+    int gv_avail = L.gvis_max;
     if (own) {
         ANN_HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&w), L.total, s.stream));
     } else {
-        ANN_REQUIRE(s.workspace_bytes >= int64_t(L.fixed + L.slot_bytes),
+        const size_t least = ws_minimum(L);
+        ANN_REQUIRE(s.workspace_bytes >= int64_t(least),
                     "search: workspace too small (" + std::to_string(s.workspace_bytes) + " bytes, at least " +
-                        std::to_string(L.fixed + L.slot_bytes) + " needed)");
+                        std::to_string(least) + " needed)");
         ANN_REQUIRE((reinterpret_cast<uintptr_t>(w) & 15) == 0, "search: workspace must be 16-byte aligned");
-        avail = int(std::min<int64_t>(L.max_slots, (s.workspace_bytes - int64_t(L.fixed)) / int64_t(L.slot_bytes)));
+        // bitmaps first (at least one each way), then multi-sequence slots
+        const int64_t spare = s.workspace_bytes - int64_t(L.fixed);
+        if (L.gvis_max > 0)
+            gv_avail = int(std::max<int64_t>(
+                1, std::min<int64_t>(L.gvis_max, (spare - int64_t(L.slot_bytes)) / int64_t(L.gvis_each))));
+        avail = int(std::min<int64_t>(L.max_slots,
+                                      (spare - int64_t(gv_avail) * int64_t(L.gvis_each)) / int64_t(L.slot_bytes)));
     }
     // [0] overflow count, [1] work counter
     uint32_t* counters = reinterpret_cast<uint32_t*>(w);
@@ -1702,6 +1787,8 @@ int launch_search(const SearchLaunch& s) {
     uint32_t* perm = reinterpret_cast<uint32_t*>(w + o);
     o += round16(size_t(s.nq) * 4);
     o = (o + 63) & ~size_t(63);  // == L.fixed
+    uint32_t* gvis = reinterpret_cast<uint32_t*>(w + o);  // visited bitmaps
+    o += size_t(gv_avail) * L.gvis_each;
     uint8_t* gheap = w + o;
 
     // the serving order (longest budgets first) is shared by the classes;
@@ -1725,6 +1812,14 @@ int launch_search(const SearchLaunch& s) {
         SearchArgs& a2 = pl.a2;
         const int nslots = std::min(pl.max_slots, avail);
         pl.grid2 = std::min(pl.grid2, nslots);
+        if (pl.gvis) {
+            a.gvis = a2.gvis = gvis;
+            a.gvis_words = a2.gvis_words = pl.gvis_words;
+            a.gvis_slots = a2.gvis_slots = std::min(pl.gvis_slots, gv_avail);
+            pl.grid2 = std::min(pl.grid2, a.gvis_slots);
+        } else {
+            a.gvis = a2.gvis = nullptr;
+        }
         a.ovf_count = a2.ovf_count = counters;
         a.ovf_list = a2.ovf_list = ovf_list;
         a.gheap = a2.gheap = gheap;

@@ -554,16 +554,31 @@ def test_one_budget_above_4096_for_more_queries_than_fit_sampled():
     np.testing.assert_array_equal(gd[rows].astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
 
 
-def test_budget_beyond_lds_is_rejected():
-    """A visited set for 2^20 evaluations cannot live in one workgroup's LDS:
-    the search says so instead of running."""
-    from paper_1312_3062_amd import _abi
-    w = synth.scaled(synth.WORKLOADS["tiny_10k_u8"], 1000, nq=2)
+def test_budget_beyond_lds_uses_a_visited_bitmap_bit_exact():
+    """Budgets whose visited set does not fit a workgroup's LDS (beyond about
+    31,000 evaluations) keep it as a bitmap over the vectors in global
+    memory: per-query budgets on both sides of the limit in one launch,
+    bit-exact against the oracle (ids, distances and traces)."""
+    w = synth.scaled(synth.WORKLOADS["sift_like_1m_u8"], 50000, nq=8, d=64, components=64)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = _index_cls().build(X, 8, 4, 16, 3, 5, 8, 4)
+    parts = idx.export()
+    ks = np.array([10, 100, 1, 10, 10, 100, 10, 1], np.int32)
+    Ts = np.array([40000, 36000, 1000, 33000, 40000, 20000, 512, 40000], np.int32)
+    gi, gd, st = gpu_search(idx, Q, 100, 40000, 64, ks=ks, Ts=Ts, stats=True)
+    assert (st[:, 6] == 0).all() and (st[:, 0] <= Ts).all()
+    print(f"[bitmap] evaluations {st[:, 0].tolist()}", flush=True)
+    assert_search_equal(idx, parts, X, Q, 100, 40000, 64, ks=ks, Ts=Ts)
+
+
+def test_exhaustive_budget_of_a_million_on_a_small_index():
+    """A budget of 2^20 on 1,000 vectors: the bitmap set, every reachable
+    vector evaluated, the same results as the oracle."""
+    w = synth.scaled(synth.WORKLOADS["tiny_10k_u8"], 1000, nq=4)
     X, Q = synth.base_vectors(w), synth.queries(w)
     idx = _index_cls().build(X, 4, 2, 4, 2, 1, 1, 0)
-    with pytest.raises(_abi.AnnError) as e:
-        idx.search_device(torch.from_numpy(Q).cuda(), 10, 1 << 20)
-    assert e.value.status == _abi.ANN_EUNSUPPORTED and "LDS" in str(e.value)
+    parts = idx.export()
+    assert_search_equal(idx, parts, X, Q, 10, 1 << 20, 64)
 
 
 # ---------------------------------------------------------------- neighborhood-graph search without bridges
