@@ -251,9 +251,11 @@ int ann_search_device(const ann_index* idx, const void* d_queries, int64_t nq, i
 
 /*
  * Device workspace for ann_search_device_ws and this request (bytes): the
- * per-query lists plus global slots for multi-sequence state that outgrows
- * LDS (256 slots up to a budget of 2048, one per resident query above it,
- * never more than the batch's queries or 512 MB).
+ * per-query lists, global slots for multi-sequence state that outgrows LDS
+ * (one per query that can be resident, never more than the batch's queries
+ * or 512 MB) and, for a budget whose visited set does not fit a
+ * workgroup's LDS (beyond about 31,000 evaluations), one visited bitmap of
+ * n bits per workgroup of that budget class (at most 1 GB of them).
  */
 int ann_search_workspace_size(const ann_index* idx, int64_t nq, int32_t k, int32_t budget,
                               const ann_search_params* params, int64_t* bytes);
