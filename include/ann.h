@@ -300,8 +300,9 @@ int ann_search_graph_device(const ann_index* idx, const void* d_queries, int64_t
  * the library runs on, held until the process ends.  Same arguments, results
  * and asynchrony as ann_search_device.
  * Errors: as ann_search_device; ANN_EINVAL when the request's smallest
- * workspace (per-query lists of about 8 bytes a query plus one
- * multi-sequence slot) exceeds the buffer: search fewer queries per call.
+ * workspace (per-query lists of about 8 bytes a query, one multi-sequence
+ * slot and, for budgets beyond LDS, one visited bitmap of n bits) exceeds
+ * the buffer: search fewer queries per call.
  * Every call on a GPU uses that GPU's one buffer: calls that overlap in time
  * on one GPU (other streams, other threads) race and must not be made.
  */
