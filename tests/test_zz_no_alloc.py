@@ -1,9 +1,10 @@
 """ann_search_device_noalloc (the search that allocates nothing, its workspace
 a buffer compiled into the library) against ann_search_device, called through
 the C ABI: bit-exact on two calls in a row, the second with a smaller input,
-on a plain index and on one whose queries move their multi-sequence state to
-global slots of the workspace; and a request too large for the buffer is
-rejected with an error."""
+on a plain index, on one whose queries move their multi-sequence state to
+global slots of the workspace and at budgets whose visited bitmaps live in
+the workspace; and a request too large for the buffer is rejected with an
+error."""
 import ctypes as C
 
 import numpy as np
@@ -52,6 +53,17 @@ def test_noalloc_equals_the_allocating_search_twice():
     _same(idx, Q, 10, 256)
     rng = np.random.default_rng(3)
     _same(idx, Q[:37], 5, 100, ks=rng.integers(1, 6, 37), Ts=rng.integers(0, 101, 37))
+
+
+def test_noalloc_with_visited_bitmaps_twice():
+    """Budgets beyond LDS: the visited bitmaps live in the buffer too."""
+    from paper_1312_3062_amd import Index
+    w = synth.scaled(synth.WORKLOADS["sift_like_1m_u8"], 50000, nq=8, d=64, components=64)
+    X, Q = synth.base_vectors(w), synth.queries(w)
+    idx = Index.build(X, 8, 4, 16, 3, 5, 8, 4)
+    print("[noalloc] 8 queries at T=40000, then 3 at T=36000", flush=True)
+    _same(idx, Q, 10, 40000)
+    _same(idx, Q[:3], 10, 36000)
 
 
 def test_noalloc_with_global_slots_twice():
