@@ -502,7 +502,7 @@ def scan_overhead_leg(idx, w, X, Q, torch, visited=10_000):
 
 
 def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 30_000, 100_000), pq_iters=4,
-                    assign_budget=256, seed=7):
+                    assign_budget=256, seed=7, cpu_sample=50):
     """Sec. 5 (Table 2's protocol on synthetic data): inverted lists over
     `lists` coarse centres (a seeded sample of the vectors, about 163 vectors
     a list as 1B / 6M in the paper), each vector assigned by the graph search
@@ -511,7 +511,10 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
     asymmetric distance.  The centres' index: kNN graph of 16, two subspaces
     of 16 codewords, every centre linked from its nearest bridge; the lists
     come from a search with budget 4W for W lists.  R@T: share of queries
-    whose true nearest neighbour is within the first T re-ranked candidates."""
+    whose true nearest neighbour is within the first T re-ranked candidates.
+    Beside each row the oracle (lists by its search over the exported
+    centres' index, then its fp64 re-ranking) is timed single-threaded on the
+    first `cpu_sample` queries, and its ids compared with the GPU's."""
     from paper_1312_3062_amd.ivf import Ivf
     qd = torch.from_numpy(Q).cuda()
     nq = len(Q)
@@ -522,9 +525,11 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
                         graph_k=16, P=2, K=16, kmeans_iters=4, bridge_t=1, bridge_b=0, centre_seed=seed)
         torch.cuda.synchronize()
         build_s = time.time() - t0
-        off = ivf.export()["list_off"].astype(np.int64)
+        parts = ivf.export()
+        off = parts["list_off"].astype(np.int64)
         sizes = np.diff(off)
         cidx = ivf.centres_index()
+        cparts = cidx.export()
         log(f"[adc] m={m}: built in {build_s:.1f}s, {lists} lists of {sizes.mean():.0f} vectors on average "
             f"(largest {sizes.max()}, empty {int((sizes == 0).sum())})")
         for L in lengths:
@@ -561,8 +566,26 @@ def graph_d_adc_leg(X, Q, gt1, torch, lists=6144, ms=(8, 16), lengths=(10_000, 3
                    "adc_GBps": round(adc_bytes / max(adc_ms, 1e-6) / 1e6, 1),
                    "adc_frac": round(adc_bytes / max(adc_ms, 1e-6) / 1e6 / HBM_PEAK_GBS, 4),
                    "build_s": round(build_s, 1)}
+            if cpu_sample:
+                import oracle
+                qs = Q[:cpu_sample]
+                t0 = time.perf_counter()
+                olists, _ = oracle.search(parts["centres"], cparts["codebooks"], cparts["graph"], cparts["bridge_off"],
+                                          cparts["bridge_ids"], qs, W, Tc, 64)
+                oids, _ = oracle.ivf_adc(qs, parts["centres"], parts["list_off"], parts["list_ids"], parts["codes"],
+                                         parts["pq"], olists, L, 100)
+                cpu_s = time.perf_counter() - t0
+                row["cpu_baseline"] = {
+                    "value": round(cpu_sample / cpu_s, 1), "unit": "queries/s", "cores": 1, "kind": "oracle",
+                    "sample": f"first {cpu_sample} queries ({cpu_s:.2f} s): the oracle's search for the lists, then "
+                              f"its fp64 re-ranking",
+                    "lists_equal": bool(np.array_equal(olists, gl[:cpu_sample])),
+                    "ids_equal_share": round(float((oids == ids[:cpu_sample]).mean()), 4)}
             log(f"[adc] m={m} L={L}: lists {W}, {row['candidates_per_query']:.0f} candidates, {rec}, "
-                f"{total_ms:.2f} ms per {nq} queries (lists {lists_ms:.2f}), {row['qps']:.0f} QPS")
+                f"{total_ms:.2f} ms per {nq} queries (lists {lists_ms:.2f}), {row['qps']:.0f} QPS"
+                + (f"; oracle {row['cpu_baseline']['value']:.0f} QPS, lists equal "
+                   f"{row['cpu_baseline']['lists_equal']}, ids equal {row['cpu_baseline']['ids_equal_share']}"
+                   if cpu_sample else ""))
             out.append(row)
         ivf.close()
     return {"lists": lists, "n": len(X), "queries": nq, "pq_iters": pq_iters, "assign_budget": assign_budget,
