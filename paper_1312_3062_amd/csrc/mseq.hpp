@@ -154,4 +154,34 @@ __device__ inline void heap_pop(HP h, int& hn, uint64_t& key, uint32_t& rk) {
     h[i] = last;
 }
 
+// Replace the smallest entry by (key, rk) and restore the order: one
+// sift-down from the root.  Taking the smallest key and inserting its
+// successor this way costs one pass that stops where the successor belongs,
+// where a pop and a push cost a pass that sinks the last entry to the bottom
+// and a second pass up.
+template <typename HP>
+__device__ inline void heap_replace_top(HP h, int hn, uint64_t key, uint32_t rk) {
+    int i = 0;
+    for (;;) {
+        const int c = 4 * i + 1;
+        if (c >= hn) break;
+        hent_t e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e[q] = h[min(c + q, hn - 1)];
+        asm volatile("" ::"v"(e[0].z), "v"(e[1].z), "v"(e[2].z), "v"(e[3].z));
+        int bc = c;
+        hent_t b = e[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+            if (c + q < hn && hkey(e[q]) < hkey(b)) {
+                b = e[q];
+                bc = c + q;
+            }
+        if (key <= hkey(b)) break;
+        h[i] = b;
+        i = bc;
+    }
+    h[i] = hmake(key, rk);
+}
+
 }  // namespace ann

@@ -683,17 +683,67 @@ struct PairMSeq {
                 of = true;
                 return false;
             }
-            uint64_t key;
-            uint32_t rk;
-            heap_pop(hp, hn, key, rk);
-            M[cnt++] = key;
-            const uint32_t ra = rk >> 8, rb = rk & 0xFF;
-            if (rb + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra, rb + 1), (ra << 8) | (rb + 1));
-            if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
+            if constexpr (FLOAT) {
+                const hent_t top = hp[0];
+                const uint64_t key = hkey(top);
+                const uint32_t rk = top.z;
+                M[cnt++] = key;
+                const uint32_t ra = rk >> 8, rb = rk & 0xFF;
+                // the successor in the row takes the top's place (none: the
+                // last entry does); a row's first element also starts the next row
+                uint64_t nk;
+                uint32_t nr;
+                if (rb + 1 < uint32_t(c.K)) {
+                    nk = inner_key(c, la, lb, ra, rb + 1);
+                    nr = (ra << 8) | (rb + 1);
+                } else {
+                    const hent_t last = hp[--hn];
+                    nk = hkey(last);
+                    nr = last.z;
+                }
+                heap_replace_top(hp, hn, nk, nr);
+                if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
+            } else {
+                uint64_t key;
+                uint32_t rk;
+                heap_pop(hp, hn, key, rk);
+                M[cnt++] = key;
+                const uint32_t ra = rk >> 8, rb = rk & 0xFF;
+                if (rb + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra, rb + 1), (ra << 8) | (rb + 1));
+                if (rb == 0 && ra + 1 < uint32_t(c.K)) heap_push(hp, hn, inner_key(c, la, lb, ra + 1, 0), (ra + 1) << 8);
+            }
         }
         sum = key_dist(M[e]);
         lid = key_id(M[e]);
         return true;
+    }
+    // element e of a side that is already materialised
+    __device__ static void known(const MSeqConf& c, bool isx, uint32_t e, uint32_t& sum, uint32_t& lid) {
+        const int nl = isx ? c.nx : c.ny;
+        const int la = isx ? c.ax : c.ay;
+        if (nl == 0) {
+            sum = 0;
+            lid = 0;
+        } else if (nl == 1) {
+            sum = c.sv[la * c.K + e];
+            lid = c.perm[la * c.K + e];
+        } else {
+            const uint64_t v = (isx ? c.m.mx : c.m.my)[e];
+            sum = key_dist(v);
+            lid = key_id(v);
+        }
+    }
+    // start row i of the outer frontier at (i, 0); Y[0] is materialised
+    __device__ void start_row(const MSeqConf& c, uint32_t i) {
+        uint32_t sx, lx, sy, ly;
+        if (!elem(c, true, i, sx, lx)) return;
+        known(c, false, 0, sy, ly);
+        if (hon >= c.m.ocap) {
+            of = true;
+            return;
+        }
+        heap_push(c.m.ho, hon, make_key(add(sx, sy), c.n + lx * c.sizeY + ly), i << 16);
+        maxf = max(maxf, hon);
     }
     __device__ void outer_push(const MSeqConf& c, uint32_t i, uint32_t j) {
         uint32_t sx, lx, sy, ly;
@@ -719,16 +769,49 @@ struct PairMSeq {
         of = false;
         if (c.nx == 2) heap_push(c.m.hx, hxn, inner_key(c, c.ax, c.bx, 0, 0), 0u);
         if (c.ny == 2) heap_push(c.m.hy, hyn, inner_key(c, c.ay, c.by, 0, 0), 0u);
-        outer_push(c, 0, 0);
+        if constexpr (FLOAT) {
+            uint32_t s0, l0;
+            if (elem(c, false, 0, s0, l0)) start_row(c, 0);
+        } else {
+            outer_push(c, 0, 0);
+        }
     }
-    // the next bridge in (distance, lid) order; false when exhausted or overflowed
+    // The next bridge in (distance, lid) order; false when exhausted or
+    // overflowed.  Float tables: the taken tuple's successor in its row
+    // replaces it at the top of the heap (one sift-down that stops where the
+    // successor belongs); the bridge-heavy float indexes spend their longest
+    // queries here.  Integer tables keep a pop and pushes: in the u8 kernels
+    // the other form cost the search loop registers.
     __device__ bool next(const MSeqConf& c, uint64_t& key) {
         if (hon == 0 || of) return false;
-        uint32_t pos;
-        heap_pop(c.m.ho, hon, key, pos);
-        const uint32_t i = pos >> 16, j = pos & 0xFFFF;
-        if (j + 1 < c.sizeY) outer_push(c, i, j + 1);
-        if (j == 0 && i + 1 < c.sizeX) outer_push(c, i + 1, 0);
+        if constexpr (FLOAT) {
+            const hent_t top = c.m.ho[0];
+            key = hkey(top);
+            const uint32_t pos = top.z;
+            const uint32_t i = pos >> 16, j = pos & 0xFFFF;
+            // (i, j + 1) takes the top's place (none, or no room for its
+            // elements: the last entry does)
+            uint32_t sx, lx, sy, ly;
+            uint64_t nk;
+            uint32_t np;
+            if (j + 1 < c.sizeY && elem(c, false, j + 1, sy, ly)) {
+                known(c, true, i, sx, lx);  // row i started with X[i]
+                nk = make_key(add(sx, sy), c.n + lx * c.sizeY + ly);
+                np = (i << 16) | (j + 1);
+            } else {
+                const hent_t last = c.m.ho[--hon];
+                nk = hkey(last);
+                np = last.z;
+            }
+            heap_replace_top(c.m.ho, hon, nk, np);
+            if (j == 0 && i + 1 < c.sizeX) start_row(c, i + 1);
+        } else {
+            uint32_t pos;
+            heap_pop(c.m.ho, hon, key, pos);
+            const uint32_t i = pos >> 16, j = pos & 0xFFFF;
+            if (j + 1 < c.sizeY) outer_push(c, i, j + 1);
+            if (j == 0 && i + 1 < c.sizeX) outer_push(c, i + 1, 0);
+        }
         return true;
     }
 };
