@@ -335,20 +335,26 @@ def test_state_capacity_by_batch_size():
     np.testing.assert_array_equal(gd[rows].astype(np.float64), np.where(np.isinf(od), 2147483647.0, od))
 
 
-def _overflow_case():
+def _overflow_case(dtype=np.uint8):
+    """65,536 bridges with lists of one.  The fp32 case holds integers and
+    keeps the sampled codewords (no k-means iteration), so that every fp32
+    distance, table entry and sum is an exact integer: the float kernels then
+    match the oracle bit for bit, like the u8 ones."""
     rng = np.random.default_rng(77)
     n = 2000
-    X = rng.integers(0, 256, size=(n, 32)).astype(np.uint8)
-    Q = rng.integers(0, 256, size=(12, 32)).astype(np.uint8)
-    idx = _index_cls().build(X, 1, 4, 16, 2, 5, 3, 1)   # 65,536 bridges, lists of one
+    X = rng.integers(0, 256, size=(n, 32)).astype(dtype)
+    Q = rng.integers(0, 256, size=(12, 32)).astype(dtype)
+    iters = 2 if dtype == np.uint8 else 0
+    idx = _index_cls().build(X, 1, 4, 16, iters, 5, 3, 1)
     return X, Q, idx, idx.export()
 
 
-def test_multisequence_overflow_moves_to_a_global_slot_exactly():
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32], ids=["u8", "f32"])
+def test_multisequence_overflow_moves_to_a_global_slot_exactly(dtype):
     """At T <= 2048, with four lists of at most 64 codewords, the LDS
     enumeration holds 8 elements per side; a query that needs more carries on
     with its state in a global slot."""
-    X, Q, idx, parts = _overflow_case()
+    X, Q, idx, parts = _overflow_case(dtype)
     gi, gd, st = gpu_search(idx, Q, 10, 1800, 64, stats=True)
     assert (st[:, 10] == 1).any()           # some queries outgrew the LDS capacity
     assert (st[:, 9] == 0).all()            # ... and found a free slot
@@ -356,10 +362,11 @@ def test_multisequence_overflow_moves_to_a_global_slot_exactly():
     assert_search_equal(idx, parts, X, Q, 10, 1800, 64)
 
 
-def test_multisequence_overflow_without_a_free_slot_is_rerun_exactly():
+@pytest.mark.parametrize("dtype", [np.uint8, np.float32], ids=["u8", "f32"])
+def test_multisequence_overflow_without_a_free_slot_is_rerun_exactly(dtype):
     """A workspace with room for one global slot: queries that find it taken
     are searched again by the second kernel, with the same results."""
-    X, Q, idx, parts = _overflow_case()
+    X, Q, idx, parts = _overflow_case(dtype)
     nq, k, T = len(Q), 10, 1800
     # at this budget the full workspace has one slot of several KB per query
     # (12 <= 256) and a few hundred bytes of lists: 3/(2 nq) of it holds the
