@@ -178,11 +178,134 @@ __global__ void __launch_bounds__(KM_THREADS) k_kmeans_assign(const uint8_t* X, 
     if (live) assign[i] = best;
 }
 
+// ----------------------------------------------------------------------
+// u8 assignment on matrix cores.  With u = x - 128 and v = c - 128 as int8,
+// |x - c|^2 = |u|^2 + |v|^2 - 2 u.v, so a point's nearest codeword minimises
+// w = |v|^2 - 2 u.v (exact in int32, |u|^2 being common to its codewords),
+// and u.v comes from v_mfma_i32_16x16x64_i8.  The subspace's codewords (at
+// most 256, ds <= 128 dimensions, a multiple of 16) sit in LDS shifted and
+// zero-padded to 64-byte k-slices (rows padded by 16 bytes for distinct
+// banks).  Four wavefronts of 64 points each keep their operands in
+// registers: lane l holds point l % 16 of each 16-point block (bytes
+// 16 (l / 16) .. +15 of a k-slice) and, per block of 16 codewords, the
+// results of points 4 (l / 16) .. +3 against codeword l % 16 of the block.
+// A key (w + 2^23) << 8 | j orders by w, then by the smaller j (the tie rule
+// of the scalar form: |w| < 2^23 at ds <= 128); the minimum over the 16 lanes
+// of a row (DPP) is the point's codeword.
+// ----------------------------------------------------------------------
+typedef int km_v4i32 __attribute__((ext_vector_type(4)));
+constexpr int KMM_MAXK = 256;
+
+template <int CTRL>
+__device__ inline uint32_t row_min_step(uint32_t v) {
+    const uint32_t o = uint32_t(__builtin_amdgcn_update_dpp(int(v), int(v), CTRL, 0xF, 0xF, false));
+    return o < v ? o : v;
+}
+
+template <int KS>
+__global__ void __launch_bounds__(256) k_kmeans_assign_mfma(const uint8_t* X, int64_t n, int d, int ds, int p, int K,
+                                                           const uint8_t* cb, int32_t* assign) {
+    constexpr int STRIDE = KS * 64 + 16;
+    constexpr int C16 = KS * 4;  // 16-byte chunks of a padded codeword
+    __shared__ __align__(16) uint8_t cw[KMM_MAXK * STRIDE];
+    __shared__ int vn[KMM_MAXK];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    for (int i = threadIdx.x; i < K * C16; i += 256) {
+        const int j = i / C16, c = i - j * C16;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (c * 16 < ds) {
+            v = *reinterpret_cast<const uint4*>(cb + int64_t(j) * ds + c * 16);
+            v.x ^= 0x80808080u;
+            v.y ^= 0x80808080u;
+            v.z ^= 0x80808080u;
+            v.w ^= 0x80808080u;
+        }
+        *reinterpret_cast<uint4*>(cw + j * STRIDE + c * 16) = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < K; j += 256) {
+        int sq = 0;
+        for (int e = 0; e < ds; ++e) {
+            const int v = int(int8_t(cw[j * STRIDE + e]));
+            sq += v * v;
+        }
+        vn[j] = sq;
+    }
+    const int64_t row0 = int64_t(blockIdx.x) * 256 + wv * 64;
+    km_v4i32 a[4][KS];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t r = min<int64_t>(row0 + rb * 16 + col, n - 1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int off = s * 64 + kq * 16;
+            uint4 v = make_uint4(0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u);  // 0 once shifted
+            if (off < ds) v = *reinterpret_cast<const uint4*>(X + r * d + int64_t(p) * ds + off);
+            a[rb][s] = km_v4i32{int(v.x ^ 0x80808080u), int(v.y ^ 0x80808080u), int(v.z ^ 0x80808080u),
+                                int(v.w ^ 0x80808080u)};
+        }
+    }
+    __syncthreads();
+    uint32_t best[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) best[rb][t] = 0xFFFFFFFFu;
+    for (int c0 = 0; c0 < K; c0 += 16) {
+        const int j = c0 + col;  // this lane's codeword; past K: read, then ignored
+        km_v4i32 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = km_v4i32{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const km_v4i32 b = *reinterpret_cast<const km_v4i32*>(cw + j * STRIDE + s * 64 + kq * 16);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[rb][s], b, acc[rb], 0, 0, 0);
+        }
+        if (j < K) {
+            const int vj = vn[j];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t key = (uint32_t(vj - 2 * acc[rb][t] + (1 << 23)) << 8) | uint32_t(j);
+                    best[rb][t] = key < best[rb][t] ? key : best[rb][t];
+                }
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            uint32_t v = best[rb][t];
+            v = row_min_step<0xB1>(v);   // quad_perm 1,0,3,2
+            v = row_min_step<0x4E>(v);   // quad_perm 2,3,0,1
+            v = row_min_step<0x141>(v);  // row_half_mirror
+            v = row_min_step<0x140>(v);  // row_mirror: the row's minimum in all 16 lanes
+            const int64_t r = row0 + rb * 16 + 4 * kq + t;
+            if (col == 0 && r < n) assign[r] = int32_t(v & 0xFFu);
+        }
+}
+
 // one assignment launch for subspace p, the register form when ds allows
 template <bool FLOAT>
 void launch_kmeans_assign(const uint8_t* X, int64_t n, int d, int ds, int p, int K, const void* cb_p, int kc,
                           int lds, int32_t* assign, hipStream_t s) {
     const dim3 grid(static_cast<unsigned>(ceil_div(n, KM_THREADS)));
+    if constexpr (!FLOAT) {
+        // matrix cores: subvectors of 16..128 bytes in 16-byte steps, rows of
+        // 16-byte multiples, at most 256 codewords
+        if (ds % 16 == 0 && ds >= 16 && ds <= 128 && d % 16 == 0 && K >= 1 && K <= KMM_MAXK) {
+            if (ds <= 64)
+                hipLaunchKernelGGL(k_kmeans_assign_mfma<1>, grid, dim3(256), 0, s, X, n, d, ds, p, K,
+                                   static_cast<const uint8_t*>(cb_p), assign);
+            else
+                hipLaunchKernelGGL(k_kmeans_assign_mfma<2>, grid, dim3(256), 0, s, X, n, d, ds, p, K,
+                                   static_cast<const uint8_t*>(cb_p), assign);
+            return;
+        }
+    }
     const bool words = FLOAT || (ds & 3) == 0;
     if (words && ds <= 16)
         hipLaunchKernelGGL((k_kmeans_assign<FLOAT, 16>), grid, dim3(KM_THREADS), lds, s, X, n, d, ds, p, K, cb_p, kc,
