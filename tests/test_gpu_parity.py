@@ -255,6 +255,19 @@ def test_variant_build_and_search_bit_exact(n, d, P, K, R, t, b, iters, hi):
         assert_search_equal(idx, parts, X, Q, k, T, L)
 
 
+@pytest.mark.parametrize("n,d,P,K,hi", [
+    (3000, 192, 2, 256, 256),   # 96-byte subvectors (a partial second k-slice), the most codewords
+    (2500, 80, 1, 200, 8),      # 80 bytes, a partial last block of codewords, tie-heavy values
+])
+def test_kmeans_on_matrix_cores_bit_exact(n, d, P, K, hi):
+    """The u8 k-means assignment on matrix cores: codebooks bit-exact against
+    the oracle's k-means (ties to the smaller codeword)."""
+    rng = np.random.default_rng(n + K)
+    X = rng.integers(0, hi, size=(n, d)).astype(np.uint8)
+    idx = _index_cls().build(X, 4, P, K, 3, 99, 1, 0)
+    np.testing.assert_array_equal(idx.export()["codebooks"], oracle.kmeans(X, P, K, 3, 99))
+
+
 def test_graph_free_index():
     """R = 0: only bridge lists are expanded."""
     rng = np.random.default_rng(5)
